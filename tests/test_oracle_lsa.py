@@ -1,0 +1,73 @@
+"""Pin of the whole oracle collision operator: the paper's linear stability results.
+
+Sec. 3.6 (tau = 0.5001, D2Q9): the present model (order 4) has no unstable
+mode at u = (0.2, 0) (Ma 0.346), neither along k_y = 0 nor anywhere in k;
+unstable modes appear by u_x = 0.248 (Ma 0.43).  Sec. 3.8.1: the order-2
+regularised model at u_x = 0.2 has an unstable shear mode along k_y = 0.
+The statements are read from tests/golden/stability.txt.
+
+Finding recorded with this pin: on a fine k-grid (513^2) the onset of the
+order-4 model lies at u_x = 0.2297; coarse grids move it (8^2: 0.2495, 16^2:
+0.2467, 24^2: 0.2325).  The paper's 0.248 is reproduced by a coarse grid; the
+test asserts only what holds on every grid: stable at 0.2, unstable at 0.248.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lsa
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "stability.txt")
+TOL = 1e-10  # |lambda| = 1 modes (conserved quantities at k = 0) carry rounding
+
+
+def rows():
+    out = []
+    for line in open(GOLDEN):
+        if line.startswith("#") or not line.strip():
+            continue
+        order, tau, ux, mach, scope, verdict = line.split()
+        out.append((int(order), float(tau), float(ux), float(mach), scope, verdict))
+    return out
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("row", rows(), ids=lambda r: f"N{r[0]}-u{r[2]}-{r[4]}")
+def test_printed_stability_statements(row):
+    order, tau, ux, mach, scope, verdict = row
+    assert ux / np.sqrt(1 / 3) == pytest.approx(mach, abs=5e-3)
+    with np.errstate(divide="ignore"):
+        if scope == "ky0":
+            kx = np.linspace(-np.pi, np.pi, 401)
+            g = lsa.dissipation_kx("D2Q9", order, tau, 1.0, [ux, 0.0], kx).max()
+        else:
+            g = max(lsa.max_growth("D2Q9", order, tau, 1.0, [ux, 0.0], nk=nk) for nk in (16, 96))
+    if verdict == "stable":
+        assert g < TOL, g
+    else:
+        assert g > 1e-7, g
+
+
+def test_rest_state_is_neutral_and_conserved_modes_have_unit_modulus():
+    """At u = 0, k = 0: three eigenvalues equal 1 (mass and momentum); none exceed 1 anywhere."""
+    lam = lsa.amplification_eigs("D2Q9", 4, 0.8, 1.0, [0.0, 0.0], 0.0, 0.0)
+    mod = np.sort(np.abs(lam).ravel())[::-1]
+    np.testing.assert_allclose(mod[:3], 1.0, atol=1e-12)
+    assert np.all(mod[3:] < 1.0 - 1e-3)
+    # non-hydrodynamic eigenvalues at k = 0 are 1 - 1/tau (the off-equilibrium relaxation) or 0
+    rest = mod[3:]
+    assert np.all(np.isclose(rest, abs(1 - 1 / 0.8), atol=1e-12) | np.isclose(rest, 0.0, atol=1e-12))
+    with np.errstate(divide="ignore"):
+        assert lsa.max_growth("D2Q9", 4, 0.8, 1.0, [0.0, 0.0], nk=32) < TOL
+
+
+def test_dissipation_of_shear_mode_matches_navier_stokes_at_small_k():
+    """Im(omega_s) = -nu k^2 and the sound modes -nu k^2 (BGK bulk viscosity), small k."""
+    tau = 0.8
+    nu = (tau - 0.5) / 3
+    k = 0.05
+    with np.errstate(divide="ignore"):
+        d = lsa.dissipation_kx("D2Q9", 4, tau, 1.0, [0.0, 0.0], np.array([k]))[0]
+    hydro = np.sort(d)[-3:]  # three least damped modes: two sound, one shear
+    np.testing.assert_allclose(hydro, -nu * k * k, rtol=2e-3)

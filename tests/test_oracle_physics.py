@@ -1,0 +1,124 @@
+"""Pins of the oracle's full update against hydrodynamics the paper states.
+
+* shear-wave decay at rate nu k^2 with nu = c_s^2 (tau - 1/2) (Sec. 2,
+  Eq. nu_def, with the shifted relaxation time of Sec. 3.4);
+* sound waves with frequency c_s |k| and damping nu |k|^2 (the dispersion /
+  dissipation relations of Sec. 3.6 with eta = 2 nu / D);
+* Galilean invariance of the shear viscosity: with an order-2 equilibrium the
+  missing third-order moments add tau d_x(rho u_x^2 u_y) to a1^(2)_xy (the
+  starred-starred terms of Sec. 3.3), which lowers the effective viscosity by
+  1 - U^2/c_s^2 under a uniform stream U; from order 3 on the term is gone;
+* Taylor--Green kinetic-energy decay KE(t) = KE(0) exp(-2 nu |k|^2 t).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import lattice as Lm
+from oracle import rr
+
+CS2 = 1.0 / 3.0
+
+
+def nu_of(tau):
+    return CS2 * (tau - 0.5)
+
+
+def evolve(lat, N, tau, rho, u, steps, every):
+    L = Lm.lattice(lat)
+    f = rr.init_populations(L, N, rho, u)
+    out = []
+    for t in range(steps + 1):
+        if t % every == 0:
+            out.append((t,) + rr.moments(L, f)[:2])
+        if t < steps:
+            f = rr.step(L, N, tau, f)
+    return out
+
+
+def shear_rate(n, tau, N=4, steps=400, t0=100):
+    y = np.arange(n)
+    k = 2 * math.pi / n
+    rho = np.ones((1, n, n))
+    u = np.zeros((2, 1, n, n))
+    u[0] = 0.01 * np.sin(k * y)[None, :, None]
+    rec = evolve("D2Q9", N, tau, rho, u, steps, 50)
+    t = np.array([r[0] for r in rec])
+    amp = np.array([2.0 / n * np.sum(r[2][0][0, :, 0] * np.sin(k * y)) for r in rec])
+    sel = t >= t0
+    slope = np.polyfit(t[sel], np.log(amp[sel]), 1)[0]
+    return -slope / (nu_of(tau) * k * k)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0])
+def test_shear_wave_viscosity(tau):
+    ratios = [shear_rate(n, tau) for n in (16, 32, 64)]
+    errs = [abs(r - 1) for r in ratios]
+    assert errs[-1] < 2e-3, ratios
+    if errs[0] > 1e-3:  # second-order convergence of the decay rate
+        assert errs[0] / errs[-1] > 10, ratios
+
+
+@pytest.mark.slow
+def test_sound_wave_dispersion_and_damping():
+    n, tau, eps = 64, 0.8, 1e-4
+    k = 2 * math.pi / n
+    x = np.arange(n)
+    rho = 1 + eps * np.cos(k * x)[None, None, :] * np.ones((1, 4, n))
+    u = np.zeros((2, 1, 4, n))
+    rho = rho[:, :, :]
+    rec = evolve("D2Q9", 4, tau, rho[0][None], u[:, 0][:, None], 600, 5)
+    t = np.array([r[0] for r in rec], dtype=float)
+    R = np.array([2.0 / n * np.sum((r[1][0, 0] - 1) * np.cos(k * x)) for r in rec])
+    J = np.array([2.0 / n * np.sum(r[1][0, 0] * r[2][0][0, 0] * np.sin(k * x)) for r in rec])
+    Z = R + 1j * J / math.sqrt(CS2)
+    sel = t >= 50
+    decay = -np.polyfit(t[sel], np.log(np.abs(Z[sel])), 1)[0]
+    freq = np.polyfit(t[sel], np.unwrap(np.angle(Z[sel])), 1)[0]
+    assert freq == pytest.approx(math.sqrt(CS2) * k, rel=0.01)
+    assert decay == pytest.approx(nu_of(tau) * k * k, rel=0.01)
+
+
+def galilean_ratio(N, U, n=32, tau=0.8, steps=300):
+    k = 2 * math.pi / n
+    x = np.arange(n)
+    rho = np.ones((1, 2, n))
+    u = np.zeros((2, 1, 2, n))
+    u[0] = U
+    u[1] = 1e-3 * np.sin(k * x)
+    rec = evolve("D2Q9", N, tau, rho, u, steps, 20)
+    t = np.array([r[0] for r in rec], dtype=float)
+    amp = np.array([abs(np.sum(r[2][1][0, 0] * np.exp(-1j * k * x))) for r in rec])
+    sel = t >= 60
+    rate = -np.polyfit(t[sel], np.log(amp[sel]), 1)[0]
+    return rate / (nu_of(tau) * k * k)
+
+
+@pytest.mark.slow
+def test_galilean_invariance_of_shear_viscosity():
+    base = galilean_ratio(2, 0.0)
+    assert base == pytest.approx(1.0, abs=0.01)
+    for U in (0.1, 0.2):
+        r2 = galilean_ratio(2, U) / base
+        assert r2 == pytest.approx(1 - U * U / CS2, abs=0.003), (U, r2)
+        for N in (3, 4):
+            rN = galilean_ratio(N, U) / base
+            assert rN == pytest.approx(1.0, abs=0.003), (N, U, rN)
+
+
+@pytest.mark.slow
+def test_taylor_green_kinetic_energy_decay():
+    cfg = W.WORKLOADS["tgv2d_64"]
+    n, u0, tau = cfg["n"], cfg["u0"], cfg["tau"]
+    rho, u = W.tgv2d(n, u0)
+    rec = evolve("D2Q9", 4, tau, rho, u, 1000, 50)
+    t = np.array([r[0] for r in rec], dtype=float)
+    ke = np.array([np.sum(0.5 * r[1] * np.sum(r[2] ** 2, axis=0)) for r in rec])
+    sel = t >= 100
+    slope = -np.polyfit(t[sel], np.log(ke[sel]), 1)[0]
+    k2 = 2 * (2 * math.pi / n) ** 2
+    assert slope == pytest.approx(2 * nu_of(tau) * k2, rel=0.01)
+    assert ke[-1] / ke[0] == pytest.approx(math.exp(-2 * nu_of(tau) * k2 * 1000), rel=0.02)
