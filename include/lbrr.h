@@ -1,0 +1,158 @@
+/*
+ * lbrr.h -- C ABI of the recursive-regularised lattice Boltzmann library
+ * (MI355X / gfx950).
+ *
+ * The library advances athermal flows on a periodic lattice with the
+ * regularised update of O. Malaspinas, "Increasing stability and accuracy of
+ * the lattice Boltzmann scheme: recursivity and regularization"
+ * (arXiv:1505.06900):
+ *
+ *   f_i(x + xi_i, t + 1) = f0_i + (1 - 1/tau) f1_i          (Sec. 3.5, Eq. discr_bgk_reg)
+ *
+ * f0 and f1 are Hermite expansions (Sec. 3.2, Eqs. fzero_d2q9 / fone_d2q9,
+ * fzero_d3q27 / fone_d3q27) truncated at order N; their coefficients are
+ * a0^(n) = rho u...u (Sec. 2) and a1^(n) from a1^(2) = P^(1) by the recursion
+ * of Sec. 3.1 (Eq. rel_a1, App. B).  tau is the shifted relaxation time of
+ * Sec. 3.4 (Eq. full_discr_bgk), so the kinematic viscosity is
+ * nu = (tau - 1/2) / 3 in lattice units.
+ *
+ * Conventions shared by every entry point
+ *  - Every function is extern "C"; none throws.  Functions returning int
+ *    return LB_OK (0) or a negative LB_ERR_* code; lb_last_error() gives a
+ *    message for the calling thread.
+ *  - Field arrays are structure-of-arrays, x fastest: rho[z][y][x],
+ *    u[d][z][y][x] (d = x, y[, z]), pi1[c][z][y][x] with the symmetric
+ *    components c = (xx, xy, yy) in 2D and (xx, xy, xz, yy, yz, zz) in 3D.
+ *    2D lattices require nz == 1.
+ *  - dtype selects the element type of caller field arrays: LB_F64 (double)
+ *    or LB_F32 (float).  on_device = 1 means the pointer is device memory of
+ *    the current HIP device, 0 means host memory.  Caller arrays are only
+ *    accessed during the call (stream-ordered on the handle's stream) and
+ *    stay owned by the caller.
+ *  - Population velocity order: i = (cx+1) + 3(cy+1) + 9(cz+1) for D2Q9
+ *    (cz = 0) and D3Q27; D3Q19 keeps the D3Q27 order without the 8 corners.
+ *  - The library owns two population buffers per handle (allocated with
+ *    hipMalloc in lb_config / lb_init_fields, freed by lb_destroy).  They
+ *    hold post-collision populations as deviations f_i - w_i rho0 in the
+ *    storage type; rho and u of the stored state equal those of the
+ *    pre-collision state at the same time because the collision conserves
+ *    them (Sec. 2, mass and momentum conservation).
+ *  - All device work is enqueued on the handle's stream (default: the null
+ *    stream).  Entry points that return host data synchronise that stream.
+ */
+#ifndef LBRR_H
+#define LBRR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_ctx* lb_handle;
+
+enum lb_lattice { LB_D2Q9 = 0, LB_D3Q19 = 1, LB_D3Q27 = 2 };
+enum lb_storage { LB_STORE_FP64 = 0, LB_STORE_FP32 = 1, LB_STORE_FP16 = 2 };
+enum lb_dtype { LB_F64 = 0, LB_F32 = 1 };
+enum lb_status {
+  LB_OK = 0,
+  LB_ERR_INVALID_ARG = -1, /* argument out of range, NULL pointer, wrong dims */
+  LB_ERR_UNSUPPORTED = -2, /* valid combination this build does not provide */
+  LB_ERR_OOM = -3,         /* device allocation failed */
+  LB_ERR_HIP = -4,         /* a HIP runtime call failed (message has the HIP error) */
+  LB_ERR_UNSTABLE = -5,    /* non-finite density or velocity found by a check */
+  LB_ERR_STATE = -6        /* call out of order (e.g. lb_step before lb_init_fields) */
+};
+
+/* Create a simulation handle.
+ * lattice: LB_D2Q9, LB_D3Q19 or LB_D3Q27 (velocity sets of Sec. 3.2).
+ * nx, ny, nz: periodic box, each >= 1, nz == 1 for D2Q9, nx*ny*nz < 2^31.
+ * tau: shifted relaxation time of Sec. 3.4, finite and > 0.5.
+ * order: Hermite truncation N of f0 and f1 (Sec. 3.2, Sec. 3.8.1 for N = 2):
+ *        2..4 for D2Q9 and D3Q19, 2..6 for D3Q27.
+ * Default storage: LB_STORE_FP32 with rho0 = 1.  No device memory is
+ * allocated and no device work is launched.  Returns NULL on error. */
+lb_handle lb_create(int lattice, int nx, int ny, int nz, double tau, int order);
+
+/* Choose population storage (LB_STORE_*) and the reference density rho0 of
+ * the deviation form f_i - w_i rho0 (rho0 > 0, finite).  FP32 and FP16
+ * storage collide in FP32, FP64 storage in FP64; FP16 values are rounded to
+ * nearest-even on store, subnormals kept.  Must precede lb_init_fields /
+ * lb_set_populations; calling it again discards the state. */
+int lb_config(lb_handle h, int storage, double rho0);
+
+/* Use hip_stream (a hipStream_t, may be NULL for the null stream) for all
+ * later device work of this handle. */
+int lb_set_stream(lb_handle h, void* hip_stream);
+
+/* Set the state at t = 0 from macroscopic fields.  The pre-collision
+ * populations are f0^(N)(rho, u) (Sec. 3.2) plus, if pi1 != NULL, the
+ * off-equilibrium part f1^(N) whose second-order coefficient is
+ * a1^(2) = pi1 (P^(1) of Sec. 2) and whose higher orders follow from the
+ * recursion of Sec. 3.1; the stored state is their collision.
+ * rho: [nz][ny][nx], u: [D][nz][ny][nx], pi1: [D(D+1)/2][nz][ny][nx] or NULL.
+ * Resets the step counter to 0. */
+int lb_init_fields(lb_handle h, const void* rho, const void* u, const void* pi1,
+                   int dtype, int on_device);
+
+/* Advance n >= 0 steps of Eq. discr_bgk_reg (pull streaming fused with the
+ * regularised collision).  Stream-ordered, asynchronous unless a stability
+ * check interval is set (lb_set_check_interval), in which case the density
+ * and velocity are checked every k steps and LB_ERR_UNSTABLE is returned
+ * after the first check that finds a non-finite value (the state then holds
+ * the failing step). */
+int lb_step(lb_handle h, long long n);
+
+/* Stability check interval k for lb_step (0 = never, the default). */
+int lb_set_check_interval(lb_handle h, long long k);
+
+/* Macroscopic fields of the current state: rho [nz][ny][nx], u [D][nz][ny][nx]
+ * and, if pi1 != NULL, the off-equilibrium stress a1^(2) of the pre-collision
+ * populations (Sec. 2, P^(1) = a1^(2)), recovered from the stored
+ * post-collision state as its a1^(2) divided by (1 - 1/tau) (LB_ERR_UNSUPPORTED
+ * when tau == 1).  Any of the outputs may be NULL.  Synchronises the stream. */
+int lb_moments(lb_handle h, void* rho, void* u, void* pi1, int dtype, int on_device);
+
+/* Global FP64 totals of the current state: out[0] = sum rho, out[1..3] =
+ * sum rho u (z component 0 in 2D), out[4] = sum rho |u|^2 / 2 (the kinetic
+ * energy followed in Sec. 4.1).  Per-wave shuffles, per-block partials, then
+ * a fixed-order final sum: bitwise reproducible.  Returns LB_ERR_UNSTABLE if
+ * any total is not finite.  Synchronises the stream. */
+int lb_reduce(lb_handle h, double out[5]);
+
+/* Volume mean of |omega|^2 / 2, omega = curl u by second-order periodic
+ * central differences, accumulated in FP64 (the enstrophy of Sec. 4.1,
+ * normalised by the number of nodes).  Synchronises the stream. */
+int lb_enstrophy(lb_handle h, double* out);
+
+/* Copy the stored post-collision deviations f_i - w_i rho0 out of / into the
+ * library, in the storage type, compact SoA [q][nz][ny][nx].  dst/src hold
+ * q*nx*ny*nz elements.  lb_set_populations makes the handle ready to step
+ * (step counter unchanged). */
+int lb_get_populations(lb_handle h, void* dst, int on_device);
+int lb_set_populations(lb_handle h, const void* src, int on_device);
+
+/* Number of completed steps since lb_init_fields. */
+long long lb_step_count(lb_handle h);
+
+/* Bytes of population storage moved per lattice-node update by lb_step:
+ * 2 * q * sizeof(storage element) (each population read once and written
+ * once).  Returns 0 for a NULL handle. */
+double lb_bytes_per_update(lb_handle h);
+
+/* Release the handle and its device buffers (NULL-safe). */
+void lb_destroy(lb_handle h);
+
+/* Thread-local description of the last error ("" if none). */
+const char* lb_last_error(void);
+
+/* Plain device copy of n bytes (n a multiple of 16, 16-byte aligned
+ * pointers) on hip_stream: the bandwidth probe and hardware-counter
+ * calibration kernel. */
+int lb_probe_copy(const void* src, void* dst, size_t n, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBRR_H */

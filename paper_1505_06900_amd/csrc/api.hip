@@ -1,0 +1,393 @@
+// C ABI of the library (declarations and contracts in include/lbrr.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbrr.h"
+#include "ops.hpp"
+
+using lbrr::LatticeOps;
+using lbrr::StepArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(LB_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), int(e));
+}
+
+#define HIP_TRY(expr, what)            \
+  do {                                 \
+    hipError_t e_ = (expr);            \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t elem_size(int storage) { return storage == LB_STORE_FP64 ? 8 : (storage == LB_STORE_FP32 ? 4 : 2); }
+
+// Extra bytes between population planes.  Planes whose size is a large power
+// of two would otherwise start at addresses that map to the same HBM
+// channels; the default adds 4 KiB + 256 B when the plane is a multiple of
+// 64 KiB.  LBRR_PLANE_PAD_BYTES overrides it (rounded up to 256 B).
+size_t plane_pad_bytes(size_t plane_bytes) {
+  if (const char* e = std::getenv("LBRR_PLANE_PAD_BYTES")) {
+    const long long v = std::atoll(e);
+    if (v >= 0) return size_t((v + 255) / 256 * 256);
+  }
+  return (plane_bytes % 65536 == 0) ? 4352 : 0;
+}
+
+}  // namespace
+
+struct lb_ctx {
+  int lattice = 0;
+  const LatticeOps* ops = nullptr;
+  int nx = 0, ny = 0, nz = 0;
+  double tau = 0.0;
+  int order = 0;
+  int storage = LB_STORE_FP32;
+  double rho0 = 1.0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t stride = 0;  // elements between population planes
+  bool ready = false;
+  long long steps = 0;
+  long long check_every = 0;
+  double* partials = nullptr;
+  int nblocks = 0;
+  double* dev_out = nullptr;
+  double* vel = nullptr;
+
+  int64_t nodes() const { return int64_t(nx) * ny * nz; }
+  int q() const { return ops->q; }
+  int d() const { return ops->d; }
+  StepArgs args() const {
+    StepArgs a;
+    a.nx = nx;
+    a.ny = ny;
+    a.nz = nz;
+    a.stride = stride;
+    a.rho0 = rho0;
+    a.omega1 = 1.0 - 1.0 / tau;
+    return a;
+  }
+  void release() {
+    for (void*& b : buf) {
+      if (b) (void)hipFree(b);
+      b = nullptr;
+    }
+    if (partials) (void)hipFree(partials);
+    if (dev_out) (void)hipFree(dev_out);
+    if (vel) (void)hipFree(vel);
+    partials = nullptr;
+    dev_out = nullptr;
+    vel = nullptr;
+    ready = false;
+  }
+};
+
+namespace {
+
+int ensure_buffers(lb_ctx* h) {
+  if (h->buf[0]) return LB_OK;
+  const size_t es = elem_size(h->storage);
+  const size_t plane = size_t(h->nodes()) * es;
+  const size_t plane_al = (plane + 255) / 256 * 256;
+  const size_t plane_bytes = plane_al + plane_pad_bytes(plane_al);
+  h->stride = int64_t(plane_bytes / es);
+  const size_t total = plane_bytes * size_t(h->q());
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipMalloc(&h->buf[k], total);
+    if (e != hipSuccess) {
+      h->release();
+      (void)hipGetLastError();
+      return fail(LB_ERR_OOM, "hipMalloc of %zu bytes for populations failed: %s", total, hipGetErrorString(e));
+    }
+  }
+  const int64_t nb = (h->nodes() + 2047) / 2048;
+  h->nblocks = int(nb < 1 ? 1 : (nb > 2048 ? 2048 : nb));
+  HIP_TRY(hipMalloc(&h->partials, sizeof(double) * 5 * h->nblocks), "hipMalloc partials");
+  HIP_TRY(hipMalloc(&h->dev_out, sizeof(double) * 8), "hipMalloc reduction output");
+  return LB_OK;
+}
+
+int check_handle(lb_ctx* h) {
+  if (!h) return fail(LB_ERR_INVALID_ARG, "NULL handle");
+  HIP_TRY(hipSetDevice(h->device), "hipSetDevice");
+  return LB_OK;
+}
+
+int totals(lb_ctx* h, double out[5]) {
+  hipError_t e = h->ops->totals(h->storage, h->buf[h->cur], h->partials, h->nblocks, h->dev_out, h->args(), h->stream);
+  if (e != hipSuccess) return hip_fail(e, "totals kernel launch");
+  HIP_TRY(hipMemcpyAsync(out, h->dev_out, sizeof(double) * 5, hipMemcpyDeviceToHost, h->stream), "copy totals");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  for (int c = 0; c < 5; ++c)
+    if (!std::isfinite(out[c])) return fail(LB_ERR_UNSTABLE, "non-finite total after step %lld", h->steps);
+  return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+lb_handle lb_create(int lattice, int nx, int ny, int nz, double tau, int order) {
+  const LatticeOps* ops = nullptr;
+  switch (lattice) {
+    case LB_D2Q9: ops = &lbrr::ops_d2q9(); break;
+    case LB_D3Q19: ops = &lbrr::ops_d3q19(); break;
+    case LB_D3Q27: ops = &lbrr::ops_d3q27(); break;
+    default: fail(LB_ERR_INVALID_ARG, "unknown lattice %d", lattice); return nullptr;
+  }
+  if (nx < 1 || ny < 1 || nz < 1 || ny > 65535 || nz > 65535) {
+    fail(LB_ERR_INVALID_ARG, "dims must be >= 1 (ny, nz <= 65535), got %d x %d x %d", nx, ny, nz);
+    return nullptr;
+  }
+  if (int64_t(nx) * ny * nz >= (int64_t(1) << 31)) {
+    fail(LB_ERR_INVALID_ARG, "nx*ny*nz must be < 2^31");
+    return nullptr;
+  }
+  if (ops->d == 2 && nz != 1) {
+    fail(LB_ERR_INVALID_ARG, "D2Q9 requires nz == 1, got %d", nz);
+    return nullptr;
+  }
+  if (!std::isfinite(tau) || !(tau > 0.5)) {
+    fail(LB_ERR_INVALID_ARG, "tau must be finite and > 0.5, got %g", tau);
+    return nullptr;
+  }
+  if (order < 2 || order > ops->nmax) {
+    fail(LB_ERR_INVALID_ARG, "order must be in [2, %d] for this lattice, got %d", ops->nmax, order);
+    return nullptr;
+  }
+  lb_ctx* h = new (std::nothrow) lb_ctx();
+  if (!h) {
+    fail(LB_ERR_OOM, "host allocation failed");
+    return nullptr;
+  }
+  h->lattice = lattice;
+  h->ops = ops;
+  h->nx = nx;
+  h->ny = ny;
+  h->nz = nz;
+  h->tau = tau;
+  h->order = order;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    fail(LB_ERR_HIP, "hipGetDevice failed");
+    return nullptr;
+  }
+  g_err.clear();
+  return h;
+}
+
+int lb_config(lb_handle h, int storage, double rho0) {
+  if (int r = check_handle(h)) return r;
+  if (storage < LB_STORE_FP64 || storage > LB_STORE_FP16) return fail(LB_ERR_INVALID_ARG, "bad storage %d", storage);
+  if (!std::isfinite(rho0) || !(rho0 > 0)) return fail(LB_ERR_INVALID_ARG, "rho0 must be finite and > 0");
+  if (h->buf[0]) HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  h->release();
+  h->storage = storage;
+  h->rho0 = rho0;
+  h->steps = 0;
+  return LB_OK;
+}
+
+int lb_set_stream(lb_handle h, void* hip_stream) {
+  if (int r = check_handle(h)) return r;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return LB_OK;
+}
+
+int lb_set_check_interval(lb_handle h, long long k) {
+  if (int r = check_handle(h)) return r;
+  if (k < 0) return fail(LB_ERR_INVALID_ARG, "check interval must be >= 0");
+  h->check_every = k;
+  return LB_OK;
+}
+
+int lb_init_fields(lb_handle h, const void* rho, const void* u, const void* pi1, int dtype, int on_device) {
+  if (int r = check_handle(h)) return r;
+  if (!rho || !u) return fail(LB_ERR_INVALID_ARG, "rho and u must not be NULL");
+  if (dtype != LB_F64 && dtype != LB_F32) return fail(LB_ERR_INVALID_ARG, "bad dtype %d", dtype);
+  if (int r = ensure_buffers(h)) return r;
+  const size_t es = dtype == LB_F64 ? 8 : 4;
+  const size_t nodes = size_t(h->nodes());
+  const int d = h->d(), nc = d * (d + 1) / 2;
+  const void *drho = rho, *du = u, *dpi = pi1;
+  void* tmp = nullptr;
+  if (!on_device) {
+    const size_t n = nodes * (1 + d + (pi1 ? nc : 0));
+    HIP_TRY(hipMalloc(&tmp, n * es), "hipMalloc staging");
+    char* t = static_cast<char*>(tmp);
+    hipError_t e = hipMemcpyAsync(t, rho, nodes * es, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t + nodes * es, u, nodes * d * es, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && pi1)
+      e = hipMemcpyAsync(t + nodes * (1 + d) * es, pi1, nodes * nc * es, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(tmp);
+      return hip_fail(e, "staging copy");
+    }
+    drho = t;
+    du = t + nodes * es;
+    dpi = pi1 ? t + nodes * (1 + d) * es : nullptr;
+  }
+  hipError_t e = h->ops->init(h->order, h->storage, dtype, drho, du, dpi, h->buf[0], h->args(), h->stream);
+  if (tmp) {
+    hipError_t s = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (e == hipSuccess) e = s;
+  }
+  if (e != hipSuccess) return hip_fail(e, "init kernel");
+  h->cur = 0;
+  h->steps = 0;
+  h->ready = true;
+  return LB_OK;
+}
+
+int lb_step(lb_handle h, long long n) {
+  if (int r = check_handle(h)) return r;
+  if (n < 0) return fail(LB_ERR_INVALID_ARG, "n must be >= 0");
+  if (!h->ready) return fail(LB_ERR_STATE, "lb_step before lb_init_fields / lb_set_populations");
+  const StepArgs a = h->args();
+  for (long long k = 0; k < n; ++k) {
+    hipError_t e = h->ops->step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    h->cur ^= 1;
+    ++h->steps;
+    if (h->check_every > 0 && h->steps % h->check_every == 0) {
+      double t[5];
+      if (int r = totals(h, t)) return r;
+    }
+  }
+  return LB_OK;
+}
+
+int lb_moments(lb_handle h, void* rho, void* u, void* pi1, int dtype, int on_device) {
+  if (int r = check_handle(h)) return r;
+  if (!h->ready) return fail(LB_ERR_STATE, "no state: call lb_init_fields or lb_set_populations first");
+  if (dtype != LB_F64 && dtype != LB_F32) return fail(LB_ERR_INVALID_ARG, "bad dtype %d", dtype);
+  const double om = 1.0 - 1.0 / h->tau;
+  if (pi1 && om == 0.0) return fail(LB_ERR_UNSUPPORTED, "pi1 is not recoverable from the stored state when tau == 1");
+  const double inv_om = pi1 ? 1.0 / om : 0.0;
+  const size_t es = dtype == LB_F64 ? 8 : 4;
+  const size_t nodes = size_t(h->nodes());
+  const int d = h->d(), nc = d * (d + 1) / 2;
+  if (on_device) {
+    hipError_t e = h->ops->moments(h->storage, dtype, h->buf[h->cur], rho, u, pi1, h->args(), inv_om, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "moments kernel");
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return LB_OK;
+  }
+  void* tmp = nullptr;
+  HIP_TRY(hipMalloc(&tmp, nodes * (1 + d + nc) * es), "hipMalloc staging");
+  char* t = static_cast<char*>(tmp);
+  void* drho = rho ? t : nullptr;
+  void* du = u ? t + nodes * es : nullptr;
+  void* dpi = pi1 ? t + nodes * (1 + d) * es : nullptr;
+  hipError_t e = h->ops->moments(h->storage, dtype, h->buf[h->cur], drho, du, dpi, h->args(), inv_om, h->stream);
+  if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, drho, nodes * es, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && u) e = hipMemcpyAsync(u, du, nodes * d * es, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && pi1) e = hipMemcpyAsync(pi1, dpi, nodes * nc * es, hipMemcpyDeviceToHost, h->stream);
+  hipError_t s = hipStreamSynchronize(h->stream);
+  (void)hipFree(tmp);
+  if (e == hipSuccess) e = s;
+  if (e != hipSuccess) return hip_fail(e, "moments");
+  return LB_OK;
+}
+
+int lb_reduce(lb_handle h, double out[5]) {
+  if (int r = check_handle(h)) return r;
+  if (!out) return fail(LB_ERR_INVALID_ARG, "out must not be NULL");
+  if (!h->ready) return fail(LB_ERR_STATE, "no state");
+  return totals(h, out);
+}
+
+int lb_enstrophy(lb_handle h, double* out) {
+  if (int r = check_handle(h)) return r;
+  if (!out) return fail(LB_ERR_INVALID_ARG, "out must not be NULL");
+  if (!h->ready) return fail(LB_ERR_STATE, "no state");
+  if (!h->vel) HIP_TRY(hipMalloc(&h->vel, sizeof(double) * size_t(h->nodes()) * h->d()), "hipMalloc velocity");
+  hipError_t e = h->ops->velocity(h->storage, h->buf[h->cur], h->vel, h->args(), h->stream);
+  if (e == hipSuccess)
+    e = lbrr::launch_enstrophy(h->vel, h->d(), h->nx, h->ny, h->nz, h->partials, h->nblocks, h->dev_out, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "enstrophy kernels");
+  double s = 0.0;
+  HIP_TRY(hipMemcpyAsync(&s, h->dev_out, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy enstrophy");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  *out = s / double(h->nodes());
+  if (!std::isfinite(*out)) return fail(LB_ERR_UNSTABLE, "non-finite enstrophy");
+  return LB_OK;
+}
+
+int lb_get_populations(lb_handle h, void* dst, int on_device) {
+  if (int r = check_handle(h)) return r;
+  if (!dst) return fail(LB_ERR_INVALID_ARG, "dst must not be NULL");
+  if (!h->ready) return fail(LB_ERR_STATE, "no state");
+  const size_t es = elem_size(h->storage);
+  const size_t row = size_t(h->nodes()) * es;
+  HIP_TRY(hipMemcpy2DAsync(dst, row, h->buf[h->cur], size_t(h->stride) * es, row, h->q(),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream),
+          "copy populations out");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return LB_OK;
+}
+
+int lb_set_populations(lb_handle h, const void* src, int on_device) {
+  if (int r = check_handle(h)) return r;
+  if (!src) return fail(LB_ERR_INVALID_ARG, "src must not be NULL");
+  if (int r = ensure_buffers(h)) return r;
+  const size_t es = elem_size(h->storage);
+  const size_t row = size_t(h->nodes()) * es;
+  HIP_TRY(hipMemcpy2DAsync(h->buf[h->cur], size_t(h->stride) * es, src, row, row, h->q(),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream),
+          "copy populations in");
+  HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  h->ready = true;
+  return LB_OK;
+}
+
+long long lb_step_count(lb_handle h) { return h ? h->steps : -1; }
+
+double lb_bytes_per_update(lb_handle h) {
+  if (!h) return 0.0;
+  return 2.0 * h->q() * double(elem_size(h->storage));
+}
+
+void lb_destroy(lb_handle h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  if (h->buf[0]) (void)hipStreamSynchronize(h->stream);
+  h->release();
+  delete h;
+}
+
+int lb_probe_copy(const void* src, void* dst, size_t n, void* hip_stream) {
+  if (!src || !dst) return fail(LB_ERR_INVALID_ARG, "NULL pointer");
+  if (n % 16 || (reinterpret_cast<uintptr_t>(src) % 16) || (reinterpret_cast<uintptr_t>(dst) % 16))
+    return fail(LB_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and a size multiple of 16");
+  hipError_t e = lbrr::launch_copy(src, dst, n, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "copy kernel");
+  return LB_OK;
+}
+
+}  // extern "C"

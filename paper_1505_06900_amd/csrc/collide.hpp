@@ -1,0 +1,421 @@
+// Register-resident recursive-regularised collision for one lattice node.
+//
+// Input: the q pulled pre-collision populations of a node, stored as
+// deviations d_i = f_i - w_i rho0.  Output (in place): the post-collision
+// deviations of Eq. discr_bgk_reg (Sec. 3.5),
+//
+//   f_i = w_i sum_{|k| <= N} H_k(xi_i) [a0_k + (1 - 1/tau) a1_k] / N_k,
+//
+// with a0_k = rho u_x^a u_y^b u_z^c (Sec. 2 and the equilibrium recursion of
+// Sec. 3.1), a1^(2) = Pi - rho c_s^2 I - rho u u (Sec. 2, P^(1) = a1^(2)) and
+// the higher a1_k from the recursion of Sec. 3.1 (Eq. rel_a1) in its closed
+// pair-sum form: every pair of indices of k carries a1^(2), the remaining
+// indices carry velocities (App. B lists the same expressions order by order,
+// with the discrete O(Ma^(n+1)) terms dropped as the paper does).
+//
+// Formulation (differs from a dense q x q projection on purpose):
+//  * moments and reconstruction of the tensor-product lattices (D2Q9, D3Q27)
+//    are done axis by axis with three-point transforms, which folds the
+//    weights w_i and the Hermite norms N_k = a! b! c! c_s^(2|k|) into
+//    per-axis constants;
+//  * D3Q19 has no orthogonal Hermite basis (Sec. 3.2): its kept polynomials
+//    are those with at least one zero exponent, and the reconstruction solves
+//    with their Gram matrix G_kl = sum_i w_i H_k H_l, computed at compile time,
+//    before the same unweighted per-axis transforms and a final w_i.
+// Everything is unrolled at compile time; coefficients beyond order N are
+// never formed.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+#include "lattice.hpp"
+
+namespace lbrr {
+
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+// Raw moments of the deviations: 0th, 1st and 2nd order.
+template <class R>
+struct Moments {
+  R d0, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
+};
+
+// Hydrodynamic state of a node.
+template <class R>
+struct Hydro {
+  R drho, rho, ux, uy, uz, jx, jy, jz;
+  R axx, ayy, azz, axy, axz, ayz;  // a1^(2) of the pre-collision populations
+};
+
+// ---- moments -------------------------------------------------------------
+
+// Tensor-product lattices: sums along x, then y, then z.  f is indexed by the
+// D3Q27 position (cx+1) + 3(cy+1) + 9(cz+1) restricted to the lattice.
+template <class L, class R>
+__device__ __forceinline__ Moments<R> moments_product(const R* f) {
+  constexpr int NZ = (L::D == 3) ? 3 : 1;
+  R X[3][3][3];  // X[a][cy][cz] = sum_cx cx^a f
+  sfor<0, NZ>([&](auto Z) {
+    sfor<0, 3>([&](auto Y) {
+      constexpr int base = 3 * Y + 9 * Z;
+      const R fm = f[base + 0], f0 = f[base + 1], fp = f[base + 2];
+      const R s = fp + fm;
+      X[0][Y][Z] = s + f0;
+      X[1][Y][Z] = fp - fm;
+      X[2][Y][Z] = s;
+    });
+  });
+  R Yv[3][3][3];  // Yv[a][b][cz] = sum_{cx,cy} cx^a cy^b f, a + b <= 2
+  sfor<0, NZ>([&](auto Z) {
+    sfor<0, 3>([&](auto A) {
+      const R m = X[A][0][Z], z0 = X[A][1][Z], p = X[A][2][Z];
+      const R s = p + m;
+      Yv[A][0][Z] = s + z0;
+      if constexpr (A <= 1) Yv[A][1][Z] = p - m;
+      if constexpr (A == 0) Yv[A][2][Z] = s;
+    });
+  });
+  Moments<R> r;
+  if constexpr (L::D == 2) {
+    r.d0 = Yv[0][0][0];
+    r.jx = Yv[1][0][0];
+    r.jy = Yv[0][1][0];
+    r.jz = R(0);
+    r.pxx = Yv[2][0][0];
+    r.pyy = Yv[0][2][0];
+    r.pxy = Yv[1][1][0];
+    r.pzz = r.pxz = r.pyz = R(0);
+  } else {
+    auto zs = [&](int a, int b, R& m0, R& m1, R& m2, int need) {
+      const R m = Yv[a][b][0], z0 = Yv[a][b][1], p = Yv[a][b][2];
+      const R s = p + m;
+      m0 = s + z0;
+      if (need >= 1) m1 = p - m;
+      if (need >= 2) m2 = s;
+    };
+    R t0, t1, t2;
+    zs(0, 0, r.d0, r.jz, r.pzz, 2);
+    zs(1, 0, r.jx, r.pxz, t2, 1);
+    zs(0, 1, r.jy, r.pyz, t2, 1);
+    zs(2, 0, r.pxx, t1, t2, 0);
+    zs(0, 2, r.pyy, t1, t2, 0);
+    zs(1, 1, r.pxy, t1, t2, 0);
+    (void)t0;
+  }
+  return r;
+}
+
+// Sum over the q velocities of cx^A cy^B cz^C f_i (zero terms dropped at compile time).
+template <class L, int A, int B, int C, class R>
+__device__ __forceinline__ R moment_direct(const R* f) {
+  R s = R(-0.0);  // -0 + x == x exactly, so the first add folds away
+  sfor<0, L::Q>([&](auto I) {
+    constexpr int p = (A == 0 ? 1 : (A == 1 ? L::cx(I) : L::cx(I) * L::cx(I))) *
+                      (B == 0 ? 1 : (B == 1 ? L::cy(I) : L::cy(I) * L::cy(I))) *
+                      (C == 0 ? 1 : (C == 1 ? L::cz(I) : L::cz(I) * L::cz(I)));
+    if constexpr (p == 1) s = s + f[I];
+    if constexpr (p == -1) s = s - f[I];
+  });
+  return s;
+}
+
+template <class L, class R>
+__device__ __forceinline__ Moments<R> moments_direct(const R* f) {
+  Moments<R> r;
+  r.d0 = moment_direct<L, 0, 0, 0>(f);
+  r.jx = moment_direct<L, 1, 0, 0>(f);
+  r.jy = moment_direct<L, 0, 1, 0>(f);
+  r.jz = moment_direct<L, 0, 0, 1>(f);
+  r.pxx = moment_direct<L, 2, 0, 0>(f);
+  r.pyy = moment_direct<L, 0, 2, 0>(f);
+  r.pzz = moment_direct<L, 0, 0, 2>(f);
+  r.pxy = moment_direct<L, 1, 1, 0>(f);
+  r.pxz = moment_direct<L, 1, 0, 1>(f);
+  r.pyz = moment_direct<L, 0, 1, 1>(f);
+  return r;
+}
+
+// f holds the lattice's q populations in lattice order.
+template <class L, class R>
+__device__ __forceinline__ Moments<R> raw_moments(const R* f) {
+  if constexpr (L::kProduct) {
+    // product lattices keep the D3Q27 positions (D2Q9: cz = 0 plane, offset 0)
+    return moments_product<L, R>(f);
+  } else {
+    return moments_direct<L, R>(f);
+  }
+}
+
+// rho, u and a1^(2) = Pi - rho cs2 I - rho u u, written with deviations:
+// Pi_ab = P'_ab + rho0 cs2 delta_ab, so a1_ab = P'_ab - drho cs2 delta_ab - j_a u_b.
+template <class L, class R>
+__device__ __forceinline__ Hydro<R> hydro(const Moments<R>& m, R rho0) {
+  constexpr R cs2 = R(kCs2);
+  Hydro<R> h;
+  h.drho = m.d0;
+  h.rho = rho0 + m.d0;
+  const R inv = R(1) / h.rho;
+  h.jx = m.jx;
+  h.jy = m.jy;
+  h.ux = m.jx * inv;
+  h.uy = m.jy * inv;
+  h.axx = m.pxx - m.d0 * cs2 - m.jx * h.ux;
+  h.ayy = m.pyy - m.d0 * cs2 - m.jy * h.uy;
+  h.axy = m.pxy - m.jx * h.uy;
+  if constexpr (L::D == 3) {
+    h.jz = m.jz;
+    h.uz = m.jz * inv;
+    h.azz = m.pzz - m.d0 * cs2 - m.jz * h.uz;
+    h.axz = m.pxz - m.jx * h.uz;
+    h.ayz = m.pyz - m.jy * h.uz;
+  } else {
+    h.jz = h.uz = h.azz = h.axz = h.ayz = R(0);
+  }
+  return h;
+}
+
+// ---- Hermite coefficients --------------------------------------------------
+
+// Is multi-index (a, b, c) carried by lattice L at order N?
+template <class L, int N>
+constexpr bool kept(int a, int b, int c) {
+  if (a + b + c > N) return false;
+  if (L::D == 2 && c != 0) return false;
+  if (!L::kProduct && a > 0 && b > 0 && c > 0) return false;  // D3Q19 basis
+  return true;
+}
+
+// C[a][b][c] = a0_k + omega1 * a1_k for every kept k (deviation form: C[0][0][0] = drho).
+// s_xx .. s_yz are omega1 * a1^(2).
+template <class L, int N, class R>
+__device__ __forceinline__ void coefficients(const Hydro<R>& h, R omega1, R (&C)[3][3][3]) {
+  const R sxx = omega1 * h.axx, syy = omega1 * h.ayy, sxy = omega1 * h.axy;
+  const R szz = omega1 * h.azz, sxz = omega1 * h.axz, syz = omega1 * h.ayz;
+  const R px[3] = {R(1), h.ux, h.ux * h.ux};
+  const R py[3] = {R(1), h.uy, h.uy * h.uy};
+  const R pz[3] = {R(1), h.uz, h.uz * h.uz};
+  sfor<0, 3>([&](auto A) {
+    sfor<0, 3>([&](auto B) {
+      sfor<0, 3>([&](auto Cc) {
+        constexpr int a = A, b = B, c = Cc;
+        if constexpr (kept<L, N>(a, b, c)) {
+          constexpr int n = a + b + c;
+          if constexpr (n == 0) {
+            C[a][b][c] = h.drho;
+          } else if constexpr (n == 1) {
+            C[a][b][c] = (a == 1) ? h.jx : ((b == 1) ? h.jy : h.jz);
+          } else {
+            // a0: rho u^k, written as j_d times the remaining velocities
+            R e;
+            if constexpr (a > 0) e = h.jx * px[a - 1] * py[b] * pz[c];
+            else if constexpr (b > 0) e = h.jy * py[b - 1] * pz[c];
+            else e = h.jz * pz[c - 1];
+            // a1: pair sum of the recursion
+            R s = R(-0.0);
+            if constexpr (a == 2) s = s + sxx * py[b] * pz[c];
+            if constexpr (b == 2) s = s + syy * px[a] * pz[c];
+            if constexpr (c == 2) s = s + szz * px[a] * py[b];
+            if constexpr (a > 0 && b > 0) s = s + R(a * b) * sxy * px[a - 1] * py[b - 1] * pz[c];
+            if constexpr (a > 0 && c > 0) s = s + R(a * c) * sxz * px[a - 1] * py[b] * pz[c - 1];
+            if constexpr (b > 0 && c > 0) s = s + R(b * c) * syz * px[a] * py[b - 1] * pz[c - 1];
+            C[a][b][c] = e + s;
+          }
+        }
+      });
+    });
+  });
+}
+
+// ---- reconstruction ---------------------------------------------------------
+
+// Three-point transform along one axis.  Weighted (product lattices): values
+// w(xi) sum_a h_a(xi) C_a / n_a at xi = -1, 0, 1 with h = (1, xi, xi^2 - 1/3),
+// w = (1/6, 2/3, 1/6) and n_a = (1, 1/3, 2/9):
+//   g(0) = 2/3 C0 - C2,  g(+-1) = 1/6 C0 +- 1/2 C1 + 1/2 C2.
+// Plain (D3Q19, after the Gram solve): g(0) = C0 - C2/3, g(+-1) = C0 +- C1 + 2/3 C2.
+template <bool Weighted, bool Has1, bool Has2, class R>
+__device__ __forceinline__ void axis3(R c0, R c1, R c2, R& gm, R& g0, R& gp) {
+  if constexpr (Weighted) {
+    R t = R(1.0 / 6.0) * c0;
+    if constexpr (Has2) t = t + R(0.5) * c2;
+    if constexpr (Has1) {
+      const R h = R(0.5) * c1;
+      gm = t - h;
+      gp = t + h;
+    } else {
+      gm = t;
+      gp = t;
+    }
+    g0 = Has2 ? R(2.0 / 3.0) * c0 - c2 : R(2.0 / 3.0) * c0;
+  } else {
+    R t = c0;
+    if constexpr (Has2) t = t + R(2.0 / 3.0) * c2;
+    if constexpr (Has1) {
+      gm = t - c1;
+      gp = t + c1;
+    } else {
+      gm = t;
+      gp = t;
+    }
+    g0 = Has2 ? c0 - R(1.0 / 3.0) * c2 : c0;
+  }
+}
+
+// Gram matrix of the kept D3Q19 polynomials and its inverse (compile time).
+template <int N>
+struct GramD3Q19 {
+  double inv[27][27];
+  static constexpr double h(int n, int c) { return n == 0 ? 1.0 : (n == 1 ? double(c) : double(c * c) - kCs2); }
+  constexpr GramD3Q19() : inv{} {
+    int ks[27] = {};
+    int K = 0;
+    for (int p = 0; p < 27; ++p)
+      if (kept<D3Q19, N>(p / 9, (p / 3) % 3, p % 3)) ks[K++] = p;
+    int vx[D3Q19::Q] = {}, vy[D3Q19::Q] = {}, vz[D3Q19::Q] = {};
+    double wv[D3Q19::Q] = {};
+    for (int j = 0, i = 0; j < 27; ++j) {  // the 19 non-corner velocities in lattice order
+      const int a = j % 3 - 1, b = (j / 3) % 3 - 1, c = j / 9 - 1;
+      const int s2 = a * a + b * b + c * c;
+      if (s2 > 2) continue;
+      vx[i] = a;
+      vy[i] = b;
+      vz[i] = c;
+      wv[i] = s2 == 0 ? 1.0 / 3.0 : (s2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+      ++i;
+    }
+    double hv[27][D3Q19::Q] = {};  // H_k(xi_i) of the kept polynomials
+    for (int r = 0; r < K; ++r)
+      for (int i = 0; i < D3Q19::Q; ++i)
+        hv[r][i] = h(ks[r] / 9, vx[i]) * h((ks[r] / 3) % 3, vy[i]) * h(ks[r] % 3, vz[i]);
+    double g[27][54] = {};
+    for (int r = 0; r < K; ++r) {
+      for (int s = 0; s < K; ++s) {
+        double acc = 0.0;
+        for (int i = 0; i < D3Q19::Q; ++i) acc += wv[i] * hv[r][i] * hv[s][i];
+        g[r][s] = acc;
+      }
+      g[r][K + r] = 1.0;
+    }
+    for (int col = 0; col < K; ++col) {  // Gauss-Jordan with partial pivoting
+      int piv = col;
+      for (int r = col + 1; r < K; ++r)
+        if ((g[r][col] < 0 ? -g[r][col] : g[r][col]) > (g[piv][col] < 0 ? -g[piv][col] : g[piv][col])) piv = r;
+      for (int s = 0; s < 2 * K; ++s) {
+        const double t = g[col][s];
+        g[col][s] = g[piv][s];
+        g[piv][s] = t;
+      }
+      const double d = g[col][col];
+      for (int s = 0; s < 2 * K; ++s) g[col][s] /= d;
+      for (int r = 0; r < K; ++r) {
+        if (r == col) continue;
+        const double m = g[r][col];
+        for (int s = 0; s < 2 * K; ++s) g[r][s] -= m * g[col][s];
+      }
+    }
+    for (int r = 0; r < K; ++r)
+      for (int s = 0; s < K; ++s) {
+        double v = g[r][K + s];
+        if (v < 1e-12 && v > -1e-12) v = 0.0;  // exact zeros of the sparse inverse
+        inv[ks[r]][ks[s]] = v;
+      }
+  }
+};
+
+template <int N>
+struct GramD3Q19Table {
+  static constexpr GramD3Q19<N> t{};
+};
+
+// Post-collision deviations of the lattice's q populations from C.
+template <class L, int N, class R>
+__device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
+  constexpr bool W = L::kProduct;
+  R B[3][3][3];
+  if constexpr (W) {
+    sfor<0, 27>([&](auto P) {
+      constexpr int a = P / 9, b = (P / 3) % 3, c = P % 3;
+      if constexpr (kept<L, N>(a, b, c)) B[a][b][c] = C[a][b][c];
+    });
+  } else {
+    // D3Q19: B = G^-1 C over the kept polynomials
+    sfor<0, 27>([&](auto P) {
+      constexpr int a = P / 9, b = (P / 3) % 3, c = P % 3;
+      if constexpr (kept<L, N>(a, b, c)) {
+        R s = R(-0.0);
+        sfor<0, 27>([&](auto S) {
+          constexpr int a2 = S / 9, b2 = (S / 3) % 3, c2 = S % 3;
+          if constexpr (kept<L, N>(a2, b2, c2)) {
+            constexpr double g = GramD3Q19Table<N>::t.inv[P][S];
+            if constexpr (g != 0.0) s = s + R(g) * C[a2][b2][c2];
+          }
+        });
+        B[a][b][c] = s;
+      }
+    });
+  }
+  // stage z: B[a][b][*] -> G1[a][b][cz]
+  constexpr int NZ = (L::D == 3) ? 3 : 1;
+  R G1[3][3][3];
+  sfor<0, 3>([&](auto A) {
+    sfor<0, 3>([&](auto Bi) {
+      constexpr int a = A, b = Bi;
+      if constexpr (kept<L, N>(a, b, 0)) {
+        if constexpr (L::D == 3) {
+          constexpr bool h1 = kept<L, N>(a, b, 1), h2 = kept<L, N>(a, b, 2);
+          axis3<W, h1, h2>(B[a][b][0], h1 ? B[a][b][1] : R(0), h2 ? B[a][b][2] : R(0),
+                           G1[a][b][0], G1[a][b][1], G1[a][b][2]);
+        } else {
+          G1[a][b][0] = B[a][b][0];
+        }
+      }
+    });
+  });
+  // presence of G1[a][b][*]: some kept (a, b, c)
+  // stage y: G1[a][*][cz] -> G2[a][cy][cz]
+  R G2[3][3][3];
+  sfor<0, 3>([&](auto A) {
+    sfor<0, NZ>([&](auto Z) {
+      constexpr int a = A;
+      if constexpr (kept<L, N>(a, 0, 0)) {
+        constexpr bool h1 = kept<L, N>(a, 1, 0), h2 = kept<L, N>(a, 2, 0);
+        axis3<W, h1, h2>(G1[a][0][Z], h1 ? G1[a][1][Z] : R(0), h2 ? G1[a][2][Z] : R(0),
+                         G2[a][0][Z], G2[a][1][Z], G2[a][2][Z]);
+      }
+    });
+  });
+  // stage x: G2[*][cy][cz] -> populations; D3Q19 multiplies by w_i and skips corners
+  sfor<0, NZ>([&](auto Z) {
+    sfor<0, 3>([&](auto Y) {
+      R gm, g0, gp;
+      axis3<W, true, true>(G2[0][Y][Z], G2[1][Y][Z], G2[2][Y][Z], gm, g0, gp);
+      sfor<0, L::Q>([&](auto I) {
+        if constexpr (L::cy(I) + 1 == Y && L::cz(I) + 1 == (L::D == 3 ? int(Z) : 1)) {
+          const R v = (L::cx(I) == -1) ? gm : ((L::cx(I) == 0) ? g0 : gp);
+          if constexpr (W) out[I] = v;
+          else out[I] = R(L::w(I)) * v;
+        }
+      });
+    });
+  });
+}
+
+// In-place collision of one node's deviations.
+template <class L, int N, class R>
+__device__ __forceinline__ Hydro<R> collide(R* f, R rho0, R omega1) {
+  const Moments<R> m = raw_moments<L, R>(f);
+  const Hydro<R> h = hydro<L, R>(m, rho0);
+  R C[3][3][3];
+  coefficients<L, N, R>(h, omega1, C);
+  reconstruct<L, N, R>(C, f);
+  return h;
+}
+
+}  // namespace lbrr

@@ -1,0 +1,358 @@
+// Device kernels of the library and their host-side launchers, templated on
+// lattice L, Hermite order N and population storage type S.  Each lattice's
+// translation unit instantiates them (kernels_d2q9.hip, kernels_d3q19.hip,
+// kernels_d3q27.hip) and exposes a LatticeOps table used by the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "collide.hpp"
+#include "ops.hpp"
+
+namespace lbrr {
+
+// storage element -> collision precision
+template <class S>
+struct Prec;
+template <>
+struct Prec<double> {
+  using R = double;
+};
+template <>
+struct Prec<float> {
+  using R = float;
+};
+template <>
+struct Prec<_Float16> {
+  using R = float;  // v_cvt_f16_f32 rounds to nearest even; f16 subnormals are kept
+};
+
+template <class S, class R>
+__device__ __forceinline__ S to_store(R v) {
+  return static_cast<S>(v);
+}
+
+// ---------------------------------------------------------------------------
+// Fused pull-streaming + regularised collision (one thread per node).
+//
+// The thread at node x gathers f_i from x - xi_i (periodic), i.e. the
+// streaming half of Eq. discr_bgk_reg, collides in registers and writes the
+// q post-collision values at its own address.  Block = a run of nodes along
+// x of one (y, z) row, so row wrap offsets are wave-uniform scalars.
+template <class L, int N, class S>
+__global__ void __launch_bounds__(256) k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
+  using R = typename Prec<S>::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.nx) return;
+  const int y = blockIdx.y, z = blockIdx.z;
+  const int xm = (x == 0) ? a.nx - 1 : x - 1;
+  const int xp = (x == a.nx - 1) ? 0 : x + 1;
+  const int ym = (y == 0) ? a.ny - 1 : y - 1;
+  const int yp = (y == a.ny - 1) ? 0 : y + 1;
+  const int zm = (z == 0) ? a.nz - 1 : z - 1;
+  const int zp = (z == a.nz - 1) ? 0 : z + 1;
+  R f[L::Q];
+  sfor<0, L::Q>([&](auto I) {
+    constexpr int cx = L::cx(I), cy = L::cy(I), cz = L::cz(I);
+    const int xs = (cx == 1) ? xm : ((cx == -1) ? xp : x);
+    const int ys = (cy == 1) ? ym : ((cy == -1) ? yp : y);
+    const int zs = (cz == 1) ? zm : ((cz == -1) ? zp : z);
+    const uint32_t off = (uint32_t(zs) * uint32_t(a.ny) + uint32_t(ys)) * uint32_t(a.nx) + uint32_t(xs);
+    const S* plane = src + int64_t(I) * a.stride;
+    f[I] = R(plane[off]);
+  });
+  collide<L, N, R>(f, R(a.rho0), R(a.omega1));
+  const uint32_t node = (uint32_t(z) * uint32_t(a.ny) + uint32_t(y)) * uint32_t(a.nx) + uint32_t(x);
+  sfor<0, L::Q>([&](auto I) { dst[int64_t(I) * a.stride + node] = to_store<S, R>(f[I]); });
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: post-collision populations of f0(rho, u) + f1(u, pi1).
+template <class L, int N, class S, class T>
+__global__ void __launch_bounds__(256) k_init(const T* __restrict__ rho, const T* __restrict__ u,
+                                              const T* __restrict__ pi1, S* __restrict__ dst, StepArgs a) {
+  using R = typename Prec<S>::R;
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  Hydro<R> h;
+  h.rho = R(rho[n]);
+  h.drho = R(double(rho[n]) - a.rho0);
+  h.ux = R(u[n]);
+  h.uy = R(u[nodes + n]);
+  h.uz = (L::D == 3) ? R(u[2 * nodes + n]) : R(0);
+  h.jx = h.rho * h.ux;
+  h.jy = h.rho * h.uy;
+  h.jz = h.rho * h.uz;
+  h.axx = h.ayy = h.azz = h.axy = h.axz = h.ayz = R(0);
+  if (pi1 != nullptr) {
+    if constexpr (L::D == 2) {
+      h.axx = R(pi1[n]);
+      h.axy = R(pi1[nodes + n]);
+      h.ayy = R(pi1[2 * nodes + n]);
+    } else {
+      h.axx = R(pi1[n]);
+      h.axy = R(pi1[nodes + n]);
+      h.axz = R(pi1[2 * nodes + n]);
+      h.ayy = R(pi1[3 * nodes + n]);
+      h.ayz = R(pi1[4 * nodes + n]);
+      h.azz = R(pi1[5 * nodes + n]);
+    }
+  }
+  R C[3][3][3];
+  coefficients<L, N, R>(h, R(a.omega1), C);
+  R f[L::Q];
+  reconstruct<L, N, R>(C, f);
+  sfor<0, L::Q>([&](auto I) { dst[int64_t(I) * a.stride + n] = to_store<S, R>(f[I]); });
+}
+
+// ---------------------------------------------------------------------------
+// Macroscopic fields of the stored (post-collision) state.
+template <class L, class S, class T>
+__global__ void __launch_bounds__(256) k_moments(const S* __restrict__ src, T* __restrict__ rho, T* __restrict__ u,
+                                                 T* __restrict__ pi1, StepArgs a, double inv_omega1) {
+  using R = typename Prec<S>::R;
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  R f[L::Q];
+  sfor<0, L::Q>([&](auto I) { f[I] = R(src[int64_t(I) * a.stride + n]); });
+  const Moments<R> m = raw_moments<L, R>(f);
+  const Hydro<R> h = hydro<L, R>(m, R(a.rho0));
+  if (rho) rho[n] = T(double(a.rho0) + double(h.drho));
+  if (u) {
+    u[n] = T(h.ux);
+    u[nodes + n] = T(h.uy);
+    if constexpr (L::D == 3) u[2 * nodes + n] = T(h.uz);
+  }
+  if (pi1) {
+    const R s = R(inv_omega1);
+    if constexpr (L::D == 2) {
+      pi1[n] = T(h.axx * s);
+      pi1[nodes + n] = T(h.axy * s);
+      pi1[2 * nodes + n] = T(h.ayy * s);
+    } else {
+      pi1[n] = T(h.axx * s);
+      pi1[nodes + n] = T(h.axy * s);
+      pi1[2 * nodes + n] = T(h.axz * s);
+      pi1[3 * nodes + n] = T(h.ayy * s);
+      pi1[4 * nodes + n] = T(h.ayz * s);
+      pi1[5 * nodes + n] = T(h.azz * s);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions: wave butterfly (64 lanes) -> LDS across waves -> one
+// partial per block; the final sum over blocks runs in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restrict__ out) {
+  __shared__ double lds[NV][kReduceBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    const double s = wave_sum(v[c]);
+    if (lane == 0) lds[c][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < kReduceBlock / 64; ++w) s += lds[threadIdx.x][w];
+    out[int64_t(blockIdx.x) * NV + threadIdx.x] = s;
+  }
+}
+
+// Per-block partial totals {rho, rho u_x, rho u_y, rho u_z, rho |u|^2 / 2}.
+template <class L, class S>
+__global__ void __launch_bounds__(kReduceBlock) k_totals(const S* __restrict__ src, double* __restrict__ partials,
+                                                         StepArgs a, int64_t per_block) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t begin = int64_t(blockIdx.x) * per_block;
+  const int64_t end = begin + per_block < nodes ? begin + per_block : nodes;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t n = begin + threadIdx.x; n < end; n += kReduceBlock) {
+    double f[L::Q];
+    sfor<0, L::Q>([&](auto I) { f[I] = double(src[int64_t(I) * a.stride + n]); });
+    const Moments<double> m = raw_moments<L, double>(f);
+    const double rho = a.rho0 + m.d0;
+    acc[0] += rho;
+    acc[1] += m.jx;
+    acc[2] += m.jy;
+    acc[3] += m.jz;
+    acc[4] += 0.5 * (m.jx * m.jx + m.jy * m.jy + m.jz * m.jz) / rho;
+  }
+  block_sum_store<5>(acc, partials);
+}
+
+// Sum of per-block partials in a fixed order: thread t adds blocks t, t+B, ...
+// then a fixed tree over the threads.
+template <int NV>
+__global__ void __launch_bounds__(kReduceBlock) k_final(const double* __restrict__ partials, int nblocks,
+                                                        double* __restrict__ out) {
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kReduceBlock) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[c] += partials[int64_t(b) * NV + c];
+  }
+  block_sum_store<NV>(acc, out);
+}
+
+// Velocity field (FP64) of the stored state, for the vorticity diagnostic.
+template <class L, class S>
+__global__ void __launch_bounds__(256) k_velocity(const S* __restrict__ src, double* __restrict__ u, StepArgs a) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  double f[L::Q];
+  sfor<0, L::Q>([&](auto I) { f[I] = double(src[int64_t(I) * a.stride + n]); });
+  const Moments<double> m = raw_moments<L, double>(f);
+  const double inv = 1.0 / (a.rho0 + m.d0);
+  u[n] = m.jx * inv;
+  u[nodes + n] = m.jy * inv;
+  if constexpr (L::D == 3) u[2 * nodes + n] = m.jz * inv;
+}
+
+// ---------------------------------------------------------------------------
+template <class L, int N, class S>
+hipError_t launch_step(const void* src, void* dst, const StepArgs& a, hipStream_t s) {
+  const int bx = a.nx >= 256 ? 256 : ((a.nx + 63) / 64) * 64;
+  dim3 grid((a.nx + bx - 1) / bx, a.ny, a.nz);
+  hipLaunchKernelGGL((k_step<L, N, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst), a);
+  return hipGetLastError();
+}
+
+template <class L, int N, class S>
+hipError_t launch_init(int dtype, const void* rho, const void* u, const void* pi1, void* dst, const StepArgs& a,
+                       hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  dim3 grid(unsigned((nodes + 255) / 256));
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_init<L, N, S, double>), grid, dim3(256), 0, s, static_cast<const double*>(rho),
+                       static_cast<const double*>(u), static_cast<const double*>(pi1), static_cast<S*>(dst), a);
+  else
+    hipLaunchKernelGGL((k_init<L, N, S, float>), grid, dim3(256), 0, s, static_cast<const float*>(rho),
+                       static_cast<const float*>(u), static_cast<const float*>(pi1), static_cast<S*>(dst), a);
+  return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_moments(int dtype, const void* src, void* rho, void* u, void* pi1, const StepArgs& a,
+                          double inv_omega1, hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  dim3 grid(unsigned((nodes + 255) / 256));
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_moments<L, S, double>), grid, dim3(256), 0, s, static_cast<const S*>(src),
+                       static_cast<double*>(rho), static_cast<double*>(u), static_cast<double*>(pi1), a, inv_omega1);
+  else
+    hipLaunchKernelGGL((k_moments<L, S, float>), grid, dim3(256), 0, s, static_cast<const S*>(src),
+                       static_cast<float*>(rho), static_cast<float*>(u), static_cast<float*>(pi1), a, inv_omega1);
+  return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_totals(const void* src, double* partials, int nblocks, double* out, const StepArgs& a,
+                         hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t per_block = (nodes + nblocks - 1) / nblocks;
+  hipLaunchKernelGGL((k_totals<L, S>), dim3(nblocks), dim3(kReduceBlock), 0, s, static_cast<const S*>(src), partials,
+                     a, per_block);
+  hipLaunchKernelGGL((k_final<5>), dim3(1), dim3(kReduceBlock), 0, s, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_velocity(const void* src, double* u, const StepArgs& a, hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  hipLaunchKernelGGL((k_velocity<L, S>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const S*>(src), u, a);
+  return hipGetLastError();
+}
+
+// order dispatch: N in [2, L::NMAX]
+template <class L, class S>
+hipError_t step_by_order(int order, const void* src, void* dst, const StepArgs& a, hipStream_t s) {
+  switch (order) {
+    case 2: return launch_step<L, 2, S>(src, dst, a, s);
+    case 3: return launch_step<L, 3, S>(src, dst, a, s);
+    case 4: return launch_step<L, 4, S>(src, dst, a, s);
+    case 5: if constexpr (L::NMAX >= 5) return launch_step<L, 5, S>(src, dst, a, s); break;
+    case 6: if constexpr (L::NMAX >= 6) return launch_step<L, 6, S>(src, dst, a, s); break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class L, class S>
+hipError_t init_by_order(int order, int dtype, const void* rho, const void* u, const void* pi1, void* dst,
+                         const StepArgs& a, hipStream_t s) {
+  switch (order) {
+    case 2: return launch_init<L, 2, S>(dtype, rho, u, pi1, dst, a, s);
+    case 3: return launch_init<L, 3, S>(dtype, rho, u, pi1, dst, a, s);
+    case 4: return launch_init<L, 4, S>(dtype, rho, u, pi1, dst, a, s);
+    case 5: if constexpr (L::NMAX >= 5) return launch_init<L, 5, S>(dtype, rho, u, pi1, dst, a, s); break;
+    case 6: if constexpr (L::NMAX >= 6) return launch_init<L, 6, S>(dtype, rho, u, pi1, dst, a, s); break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class L>
+struct OpsImpl {
+  static hipError_t step(int order, int storage, const void* src, void* dst, const StepArgs& a, hipStream_t s) {
+    switch (storage) {
+      case 0: return step_by_order<L, double>(order, src, dst, a, s);
+      case 1: return step_by_order<L, float>(order, src, dst, a, s);
+      case 2: return step_by_order<L, _Float16>(order, src, dst, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  static hipError_t init(int order, int storage, int dtype, const void* rho, const void* u, const void* pi1,
+                         void* dst, const StepArgs& a, hipStream_t s) {
+    switch (storage) {
+      case 0: return init_by_order<L, double>(order, dtype, rho, u, pi1, dst, a, s);
+      case 1: return init_by_order<L, float>(order, dtype, rho, u, pi1, dst, a, s);
+      case 2: return init_by_order<L, _Float16>(order, dtype, rho, u, pi1, dst, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  static hipError_t moments(int storage, int dtype, const void* src, void* rho, void* u, void* pi1,
+                            const StepArgs& a, double inv_omega1, hipStream_t s) {
+    switch (storage) {
+      case 0: return launch_moments<L, double>(dtype, src, rho, u, pi1, a, inv_omega1, s);
+      case 1: return launch_moments<L, float>(dtype, src, rho, u, pi1, a, inv_omega1, s);
+      case 2: return launch_moments<L, _Float16>(dtype, src, rho, u, pi1, a, inv_omega1, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  static hipError_t totals(int storage, const void* src, double* partials, int nblocks, double* out,
+                           const StepArgs& a, hipStream_t s) {
+    switch (storage) {
+      case 0: return launch_totals<L, double>(src, partials, nblocks, out, a, s);
+      case 1: return launch_totals<L, float>(src, partials, nblocks, out, a, s);
+      case 2: return launch_totals<L, _Float16>(src, partials, nblocks, out, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  static hipError_t velocity(int storage, const void* src, double* u, const StepArgs& a, hipStream_t s) {
+    switch (storage) {
+      case 0: return launch_velocity<L, double>(src, u, a, s);
+      case 1: return launch_velocity<L, float>(src, u, a, s);
+      case 2: return launch_velocity<L, _Float16>(src, u, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  static const LatticeOps& table() {
+    static const LatticeOps t = {L::Q, L::D, L::NMAX, &step, &init, &moments, &totals, &velocity};
+    return t;
+  }
+};
+
+}  // namespace lbrr

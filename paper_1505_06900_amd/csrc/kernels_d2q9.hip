@@ -1,0 +1,6 @@
+// Kernel instantiations for the D2Q9 lattice.
+#include "kernels.hpp"
+
+namespace lbrr {
+const LatticeOps& ops_d2q9() { return OpsImpl<D2Q9>::table(); }
+}  // namespace lbrr

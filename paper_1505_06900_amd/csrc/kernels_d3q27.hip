@@ -1,0 +1,6 @@
+// Kernel instantiations for the D3Q27 lattice.
+#include "kernels.hpp"
+
+namespace lbrr {
+const LatticeOps& ops_d3q27() { return OpsImpl<D3Q27>::table(); }
+}  // namespace lbrr

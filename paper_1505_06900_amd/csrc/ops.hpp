@@ -1,0 +1,42 @@
+// Host-side interface between the C ABI (api.hip) and the per-lattice kernel
+// translation units.  Plain function pointers; no torch types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbrr {
+
+constexpr int kReduceBlock = 256;
+
+// Launch parameters shared by the kernels.
+struct StepArgs {
+  int nx, ny, nz;
+  int64_t stride;   // elements between consecutive population planes
+  double rho0;      // reference density of the deviation storage
+  double omega1;    // 1 - 1/tau
+};
+
+struct LatticeOps {
+  int q, d, nmax;
+  hipError_t (*step)(int order, int storage, const void* src, void* dst, const StepArgs& a, hipStream_t s);
+  hipError_t (*init)(int order, int storage, int dtype, const void* rho, const void* u, const void* pi1, void* dst,
+                     const StepArgs& a, hipStream_t s);
+  hipError_t (*moments)(int storage, int dtype, const void* src, void* rho, void* u, void* pi1, const StepArgs& a,
+                        double inv_omega1, hipStream_t s);
+  hipError_t (*totals)(int storage, const void* src, double* partials, int nblocks, double* out, const StepArgs& a,
+                       hipStream_t s);
+  hipError_t (*velocity)(int storage, const void* src, double* u, const StepArgs& a, hipStream_t s);
+};
+
+const LatticeOps& ops_d2q9();
+const LatticeOps& ops_d3q19();
+const LatticeOps& ops_d3q27();
+
+// diagnostics kernels (diag.hip)
+hipError_t launch_enstrophy(const double* u, int d, int nx, int ny, int nz, double* partials, int nblocks,
+                            double* out, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, size_t n, hipStream_t s);
+
+}  // namespace lbrr

@@ -1,0 +1,61 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/lbrr.h declares with the binding's signatures, and rejects invalid
+arguments before touching a GPU.  No compute calls are made here."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbrr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(lb_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_core_entry_points():
+    names = declared_functions()
+    for n in ("lb_create", "lb_init_fields", "lb_step", "lb_moments", "lb_destroy"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported_and_bound(lbrr):
+    import ctypes
+
+    lib = ctypes.CDLL(lbrr._lib.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+        assert n in lbrr._lib.SIGNATURES, n
+        assert getattr(lbrr, n) is not None
+    assert set(lbrr._lib.SIGNATURES) == set(declared_functions())
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((7, 8, 8, 1, 0.7, 4), "unknown lattice"),
+    ((0, 8, 8, 2, 0.7, 4), "nz == 1"),
+    ((0, 0, 8, 1, 0.7, 4), "dims"),
+    ((2, 8, 8, 70000, 0.7, 4), "dims"),
+    ((2, 2048, 2048, 1024, 0.7, 4), "2^31"),
+    ((0, 8, 8, 1, 0.5, 4), "tau"),
+    ((0, 8, 8, 1, float("nan"), 4), "tau"),
+    ((0, 8, 8, 1, 0.7, 5), "order"),
+    ((1, 8, 8, 8, 0.7, 5), "order"),
+    ((2, 8, 8, 8, 0.7, 7), "order"),
+    ((2, 8, 8, 8, 0.7, 1), "order"),
+])
+def test_invalid_create_arguments_are_rejected(lbrr, args, msg):
+    h = lbrr.lb_create(*args)
+    assert not h
+    assert msg in lbrr.lb_last_error().decode()
+
+
+def test_null_handle_calls_fail_cleanly(lbrr):
+    assert lbrr.lb_step(None, 1) == lbrr.LB_ERR_INVALID_ARG
+    assert lbrr.lb_config(None, 1, 1.0) == lbrr.LB_ERR_INVALID_ARG
+    assert lbrr.lb_step_count(None) == -1
+    assert lbrr.lb_bytes_per_update(None) == 0.0
+    lbrr.lb_destroy(None)  # NULL-safe
+    assert lbrr.lb_probe_copy(None, None, 16, None) == lbrr.LB_ERR_INVALID_ARG

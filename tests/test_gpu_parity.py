@@ -1,0 +1,235 @@
+"""GPU parity: the HIP library against the FP64 oracle on the same seeded inputs.
+
+Bar (relative to the reference field):
+  rho, u      L2 and Linf <= 1e-12 with FP64 storage, <= 1e-5 with FP32;
+  pi1         <= 1e-10 (FP64) / 1e-4 (FP32): a1^(2) is a small difference of
+              O(1) moments, so its relative rounding is larger;
+  FP16        velocity error reported and bounded loosely (5e-3 after the
+              short runs here), since half-precision deviations carry about
+              11 significant bits.
+Sizes span several x-blocks with a ragged tail (nx = 300 -> blocks of 256)
+and small sub-wave rows (nx = 20), and every lattice / order / storage.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import diagnostics as OD
+from oracle import lattice as OL
+from oracle import rr
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-5, 1e-4), "fp16": (5e-3, None)}
+CASES = [(lat, N) for lat in ("D2Q9", "D3Q19", "D3Q27") for N in range(2, OL.MAX_ORDER[lat] + 1)]
+SHAPES = {2: [(1, 37, 70), (1, 9, 300)], 3: [(6, 10, 300), (12, 14, 20)]}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def rel_linf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def smooth_inputs(D, shape, seed):
+    nc = D * (D + 1) // 2
+    rho = 1.0 + W.smooth_random(1, shape, 0.02, seed)[0]
+    u = W.smooth_random(D, shape, 0.08, seed + 1)
+    pi1 = W.smooth_random(nc, shape, 2e-3, seed + 2)
+    return rho, u, pi1
+
+
+_oracle_cache = {}
+
+
+def oracle_run(lat, N, tau, shape, steps, seed):
+    key = (lat, N, tau, shape, steps, seed)
+    if key not in _oracle_cache:
+        L = OL.lattice(lat)
+        rho, u, pi1 = smooth_inputs(L.D, shape, seed)
+        f = rr.init_populations(L, N, rho, u, rr.pi1_from_components(L, pi1))
+        for _ in range(steps):
+            f = rr.step(L, N, tau, f)
+        r, v, Pi = rr.moments(L, f)
+        A = rr.pi1_components(L, rr.offeq_second(L, r, v, Pi))
+        _oracle_cache[key] = (r, v, A)
+    return _oracle_cache[key]
+
+
+def gpu_run(P, lat, N, tau, shape, steps, seed, storage):
+    D = P.DIM[lat]
+    rho, u, pi1 = smooth_inputs(D, shape, seed)
+    sim = P.Simulation(lat, shape, tau, N, storage=storage)
+    sim.init_fields(rho, u, pi1)
+    sim.step(steps)
+    r, v, p = sim.moments(pi1=True)
+    out = (r.cpu().numpy(), v.cpu().numpy(), p.cpu().numpy())
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("lat,N", CASES)
+def test_parity_with_oracle(lbrr, gpu, lat, N, storage):
+    D = lbrr.DIM[lat]
+    steps = 24 if D == 2 else 8
+    tau = 0.62
+    tol_ru, tol_pi = TOL[storage]
+    for k, shape in enumerate(SHAPES[D]):
+        print(f"case {lat} N={N} {storage} shape={shape} steps={steps}", flush=True)
+        ref = oracle_run(lat, N, tau, shape, steps, 100 + k)
+        got = gpu_run(lbrr, lat, N, tau, shape, steps, 100 + k, storage)
+        e_rho = max(rel_l2(got[0], ref[0]), rel_linf(got[0], ref[0]))
+        e_u = max(rel_l2(got[1], ref[1]), rel_linf(got[1], ref[1]))
+        e_pi = max(rel_l2(got[2], ref[2]), rel_linf(got[2], ref[2]))
+        print(f"  err rho {e_rho:.2e} u {e_u:.2e} pi1 {e_pi:.2e}", flush=True)
+        assert e_rho <= tol_ru and e_u <= tol_ru
+        if tol_pi is not None:
+            assert e_pi <= tol_pi
+
+
+@pytest.mark.parametrize("lat,N", CASES)
+def test_initial_and_one_step_populations(lbrr, gpu, lat, N):
+    """Stored post-collision deviations equal the oracle's collide(f) - w rho0, at t = 0 and after
+    one step from an arbitrary (noisy, non-equilibrium) population state set through the ABI."""
+    torch = gpu
+    L = OL.lattice(lat)
+    shape = (1, 11, 67) if L.D == 2 else (5, 7, 66)
+    rho, u, pi1 = smooth_inputs(L.D, shape, 7)
+    tau = 0.7
+    f0 = rr.init_populations(L, N, rho, u, rr.pi1_from_components(L, pi1))
+    g0 = rr.collide(L, N, tau, f0)
+    wr = L.w.reshape((-1, 1, 1, 1))
+    sim = lbrr.Simulation(lat, shape, tau, N, storage="fp64")
+    sim.init_fields(rho, u, pi1)
+    got0 = sim.get_populations().cpu().numpy()
+    scale = np.abs(g0 - wr).max()
+    assert np.abs(got0 - (g0 - wr)).max() <= 1e-13 * scale
+    g_noisy = g0 + W.noise(g0.shape, 1e-3, 9) * wr
+    sim.set_populations(torch.from_numpy(g_noisy - wr))
+    sim.step(1)
+    got1 = sim.get_populations().cpu().numpy()
+    ref1 = rr.step_post(L, N, tau, g_noisy) - wr
+    assert np.abs(got1 - ref1).max() <= 1e-13 * np.abs(ref1).max()
+    sim.close()
+
+
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q19", "D3Q27"])
+def test_totals_enstrophy_and_conservation(lbrr, gpu, lat):
+    L = OL.lattice(lat)
+    N = OL.MAX_ORDER[lat]
+    shape = (1, 48, 80) if L.D == 2 else (10, 12, 40)
+    rho, u, pi1 = smooth_inputs(L.D, shape, 21)
+    sim = lbrr.Simulation(lat, shape, 0.6, N, storage="fp64")
+    sim.init_fields(rho, u, pi1)
+    t0 = sim.reduce()
+    # oracle totals and enstrophy of the same initial state
+    f = rr.init_populations(L, N, rho, u, rr.pi1_from_components(L, pi1))
+    r, v, _ = rr.moments(L, f)
+    ref = OD.totals(r, v)
+    for a, b in zip(t0, ref):
+        assert a == pytest.approx(b, rel=1e-12, abs=1e-12 * abs(ref[0]))
+    ens = sim.enstrophy()
+    assert ens == pytest.approx(OD.enstrophy(v), rel=1e-11)
+    sim.step(50)
+    t1 = sim.reduce()
+    assert abs(t1[0] - t0[0]) <= 1e-13 * t0[0]
+    for c in (1, 2, 3):
+        assert abs(t1[c] - t0[c]) <= 1e-13 * t0[0]
+    # bitwise reproducible reduction
+    assert sim.reduce() == t1
+    sim.close()
+
+
+def test_fp32_runs_are_deterministic(lbrr, gpu):
+    shape = (8, 16, 96)
+    rho, u, pi1 = smooth_inputs(3, shape, 5)
+    outs = []
+    for _ in range(2):
+        sim = lbrr.Simulation("D3Q27", shape, 0.55, 4, storage="fp32")
+        sim.init_fields(rho, u, pi1)
+        sim.step(20)
+        outs.append(sim.get_populations().cpu().numpy())
+        sim.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_taylor_green_2d_fp64_parity_and_decay(lbrr, gpu):
+    cfg = W.WORKLOADS["tgv2d_64"]
+    n, u0, tau = cfg["n"], cfg["u0"], cfg["tau"]
+    rho, u = W.tgv2d(n, u0)
+    L = OL.lattice("D2Q9")
+    f = rr.init_populations(L, 4, rho, u)
+    sim = lbrr.Simulation("D2Q9", (1, n, n), tau, 4, storage="fp64")
+    sim.init_fields(rho, u)
+    ke = []
+    t = 0
+    for target in (100, 1000):
+        while t < target:
+            f = rr.step(L, 4, tau, f)
+            t += 1
+        sim.step(target - sim.steps)
+        r_ref, u_ref, _ = rr.moments(L, f)
+        r, v = (x.cpu().numpy() for x in sim.moments())
+        e = max(rel_l2(r, r_ref), rel_linf(r, r_ref), rel_l2(v, u_ref), rel_linf(v, u_ref))
+        print(f"TGV2D t={target} max rel err {e:.2e}", flush=True)
+        assert e <= 1e-12
+        ke.append(sim.reduce()[4])
+    nu = (tau - 0.5) / 3
+    k2 = 2 * (2 * math.pi / n) ** 2
+    assert ke[1] / ke[0] == pytest.approx(math.exp(-2 * nu * k2 * 900), rel=5e-3)
+    sim.close()
+
+
+def _neighbourhood_step(L, N, tau, nodes, g_of, shape):
+    """Post-collision populations one step later at ``nodes`` (M, 3) [z, y, x]: collide(stream(g)).
+
+    ``g_of(nodes)`` returns the (q, M') post-collision populations at an (M', 3) node array."""
+    nz, ny, nx = shape
+    c = L.c
+    src = (nodes[:, None, :] - c[None, :, ::-1]) % np.array([nz, ny, nx])  # (M, q, 3) source of each population
+    flat = src.reshape(-1, 3)
+    uniq, inv = np.unique(flat, axis=0, return_inverse=True)
+    g = g_of(uniq)                                   # (q, U)
+    pulled = g[np.tile(np.arange(L.q), len(nodes)), inv.ravel()].reshape(len(nodes), L.q).T
+    return rr.collide(L, N, tau, pulled)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp64"])
+def test_full_size_d3q27_sampled_parity(lbrr, gpu, storage):
+    """256^3 D3Q27 order 4 (the benchmark launch): two steps, sampled nodes computed by the oracle alone."""
+    cfg = W.WORKLOADS["tgv3d_256_ma01"]
+    n, tau = cfg["n"], cfg["tau"]
+    shape = (n, n, n)
+    rho, u = W.tgv3d(n, cfg["u0"])
+    L = OL.lattice("D3Q27")
+    N = 4
+    print(f"full-size D3Q27 {storage} 256^3 two steps", flush=True)
+    sim = lbrr.Simulation("D3Q27", shape, tau, N, storage=storage)
+    sim.init_fields(rho, u)
+    sim.step(2)
+    r_gpu, u_gpu = (x.cpu().numpy() for x in sim.moments())
+    sim.close()
+    rng = np.random.default_rng(0)
+    pts = np.concatenate([rng.integers(0, n, size=(24, 3)), [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0]]])
+
+    def g0(nodes):
+        z, y, x = nodes.T
+        f = rr.init_populations(L, N, rho[z, y, x], u[:, z, y, x])
+        return rr.collide(L, N, tau, f)
+
+    def g1(nodes):
+        return _neighbourhood_step(L, N, tau, nodes, g0, shape)
+
+    g2 = _neighbourhood_step(L, N, tau, pts, g1, shape)
+    r_ref, u_ref, _ = rr.moments(L, g2)
+    idx = tuple(pts.T)
+    tol = 1e-12 if storage == "fp64" else 1e-5
+    e_r = np.abs(r_gpu[idx] - r_ref).max()
+    e_u = np.abs(u_gpu[(slice(None),) + idx] - u_ref).max() / np.abs(u_ref).max()
+    print(f"  sampled err rho {e_r:.2e} u {e_u:.2e}", flush=True)
+    assert e_r <= tol and e_u <= tol
