@@ -53,9 +53,16 @@ class LBError(RuntimeError):
 
 
 def load():
-    """Load liblbrr.so (raises if it has not been built)."""
+    """Load liblbrr.so (raises if it has not been built).
+
+    torch is imported first so that its HIP runtime is the one already in the
+    process: the library's libamdhip64.so.7 dependency then binds to it, and
+    device pointers and streams from torch are valid in the library.
+    """
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (must precede the CDLL below)
+
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1505_06900_amd.build`")
         lib = ctypes.CDLL(LIB_PATH)

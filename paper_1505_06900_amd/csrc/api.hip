@@ -191,9 +191,10 @@ lb_handle lb_create(int lattice, int nx, int ny, int nz, double tau, int order) 
   h->nz = nz;
   h->tau = tau;
   h->order = order;
-  if (hipGetDevice(&h->device) != hipSuccess) {
+  const hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
     delete h;
-    fail(LB_ERR_HIP, "hipGetDevice failed");
+    fail(LB_ERR_HIP, "hipGetDevice failed: %s (%d)", hipGetErrorString(e), int(e));
     return nullptr;
   }
   g_err.clear();
