@@ -83,9 +83,82 @@ def run_gpu(P, torch, storage, rho, u, cfg, steps, warmup):
     }
     _, vel = sim.moments()
     totals = sim.reduce()
-    res["mass_drift"] = None
     sim.close()
     return res, vel, totals
+
+
+def copy_probe(P, torch, nbytes=2 << 30, reps=10):
+    """Achievable HBM rate of a plain device copy (read n + write n bytes) with the library's copy kernel."""
+    import ctypes
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    P.check(P.lb_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, sp))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        P.check(P.lb_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, sp))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"bytes_moved_per_launch": 2 * nbytes, "ms": round(ms, 4), "gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def probe(P, torch, storages, steps=5):
+    """Short fixed launch sequence for hardware-counter runs: copies of known size, then step kernels."""
+    import ctypes
+
+    import workloads as W
+
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    sp = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(3):
+        P.check(P.lb_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, sp))
+    torch.cuda.synchronize()
+    del src, dst
+    cfg = W.WORKLOADS[WORKLOAD]
+    n = cfg["n"]
+    rho, u = W.tgv3d(n, cfg["u0"])
+    for st in storages:
+        sim = P.Simulation("D3Q27", (n, n, n), cfg["tau"], cfg["order"], storage=st)
+        sim.init_fields(rho, u)
+        sim.step(steps)
+        torch.cuda.synchronize()
+        log(f"probe {st}: {steps} steps, {sim.bytes_per_update * n**3:.0f} algorithmic bytes per launch")
+        sim.close()
+    return {"copy_bytes": nbytes, "copies": 3, "storages": storages, "steps": steps, "nodes": n**3}
+
+
+def summarize_prof(paths):
+    """Text summary of rocprofv3 CSV output: kernel_stats (durations) and counter_collection (PMC)."""
+    import csv
+    import glob
+
+    lines = []
+    for root in paths:
+        for f in sorted(glob.glob(os.path.join(root, "**", "*kernel_stats.csv"), recursive=True)):
+            lines.append(f"# kernel stats: {os.path.relpath(f, root)}")
+            with open(f) as fh:
+                rows = list(csv.DictReader(fh))
+            for r in rows:
+                lines.append(f"{r['Name'][:90]:90s} calls {r['Calls']:>6s} avg_us {float(r['AverageNs'])/1e3:10.2f} "
+                             f"min_us {float(r['MinNs'])/1e3:10.2f} max_us {float(r['MaxNs'])/1e3:10.2f}")
+        for f in sorted(glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True)):
+            lines.append(f"# counters: {os.path.relpath(f, root)}")
+            acc = {}
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    key = (r["Kernel_Name"][:90], r["Counter_Name"])
+                    acc.setdefault(key, []).append(float(r["Counter_Value"]))
+            for (k, c), v in sorted(acc.items()):
+                lines.append(f"{k:90s} {c:12s} dispatches {len(v):4d} mean {sum(v)/len(v):16.1f} "
+                             f"min {min(v):16.1f} max {max(v):16.1f}")
+    return "\n".join(lines)
 
 
 def cpu_baseline(cfg, budget_s=12.0):
@@ -126,7 +199,12 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--storages", default="fp32,fp16,fp64")
+    ap.add_argument("--probe", action="store_true", help="short launch sequence for rocprofv3 counter runs")
+    ap.add_argument("--summarize-prof", nargs="+", metavar="DIR", help="summarise rocprofv3 CSV output and exit")
     a = ap.parse_args(argv)
+    if a.summarize_prof:
+        print(summarize_prof(a.summarize_prof))
+        return 0
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the domain-decomposition design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
@@ -142,6 +220,9 @@ def main(argv=None):
     import paper_1505_06900_amd as P
     import workloads as W
 
+    if a.probe:
+        print(json.dumps(probe(P, torch, a.storages.split(","))), flush=True)
+        return 0
     cfg = W.WORKLOADS[WORKLOAD]
     n = cfg["n"]
     log(f"generating {n}^3 TGV fields")
@@ -192,6 +273,8 @@ def main(argv=None):
                                "bytes_per_update": v["bytes_per_update"]} for st, v in results.items()},
         "l2_err_u_vs_fp64": {"steps": a.warmup + a.steps, **{k: float(f"{v:.3e}") for k, v in errs.items()}},
     }
+    out["copy_probe"] = copy_probe(P, torch)
+    log(f"copy probe: {out['copy_probe']['gbs']} GB/s")
     if not a.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(cfg)

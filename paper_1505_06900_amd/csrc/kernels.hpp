@@ -34,13 +34,24 @@ __device__ __forceinline__ S to_store(R v) {
   return static_cast<S>(v);
 }
 
+// Element offset of node n (linear index (z*ny + y)*nx + x) in a population array.
+__device__ __forceinline__ int64_t node_offset(const StepArgs& a, uint32_t n) {
+  const uint32_t x = n % uint32_t(a.nx), r = n / uint32_t(a.nx);
+  const uint32_t y = r % uint32_t(a.ny), z = r / uint32_t(a.ny);
+  return int64_t(z) * a.sz + int64_t(y) * a.sy + x;
+}
+
 // ---------------------------------------------------------------------------
-// Fused pull-streaming + regularised collision (one thread per node).
+// Fused pull-streaming + regularised collision, one thread per node.
 //
 // The thread at node x gathers f_i from x - xi_i (periodic), i.e. the
 // streaming half of Eq. discr_bgk_reg, collides in registers and writes the
-// q post-collision values at its own address.  Block = a run of nodes along
-// x of one (y, z) row, so row wrap offsets are wave-uniform scalars.
+// q post-collision values at its own address.  Block = a run of nodes along x
+// of one (y, z) row, so the y/z wrap and every row base are wave-uniform
+// scalars; the x +-1 neighbours are per-lane loads one element off the
+// aligned row segment, served by the same cache lines.  All q loads are in
+// flight before the first use.  Stores are non-temporal: the output is not
+// read again before the next step has streamed the whole lattice.
 template <class L, int N, class S>
 __global__ void __launch_bounds__(256) k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
   using R = typename Prec<S>::R;
@@ -59,13 +70,26 @@ __global__ void __launch_bounds__(256) k_step(const S* __restrict__ src, S* __re
     const int xs = (cx == 1) ? xm : ((cx == -1) ? xp : x);
     const int ys = (cy == 1) ? ym : ((cy == -1) ? yp : y);
     const int zs = (cz == 1) ? zm : ((cz == -1) ? zp : z);
-    const uint32_t off = (uint32_t(zs) * uint32_t(a.ny) + uint32_t(ys)) * uint32_t(a.nx) + uint32_t(xs);
-    const S* plane = src + int64_t(I) * a.stride;
-    f[I] = R(plane[off]);
+    const S* row = src + int64_t(I) * a.si + int64_t(zs) * a.sz + int64_t(ys) * a.sy;
+    f[I] = R(row[xs]);
   });
   collide<L, N, R>(f, R(a.rho0), R(a.omega1));
-  const uint32_t node = (uint32_t(z) * uint32_t(a.ny) + uint32_t(y)) * uint32_t(a.nx) + uint32_t(x);
-  sfor<0, L::Q>([&](auto I) { dst[int64_t(I) * a.stride + node] = to_store<S, R>(f[I]); });
+  S* out = dst + int64_t(z) * a.sz + int64_t(y) * a.sy + x;
+  sfor<0, L::Q>([&](auto I) { __builtin_nontemporal_store(to_store<S, R>(f[I]), out + int64_t(I) * a.si); });
+}
+
+// Copy between the internal layout and compact SoA [q][node].
+template <class L, class S>
+__global__ void __launch_bounds__(256) k_repack(const S* __restrict__ src, S* __restrict__ dst, StepArgs a,
+                                                bool to_compact) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = node_offset(a, uint32_t(n));
+  for (int i = 0; i < L::Q; ++i) {
+    if (to_compact) dst[i * nodes + n] = src[i * a.si + off];
+    else dst[i * a.si + off] = src[i * nodes + n];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -105,7 +129,8 @@ __global__ void __launch_bounds__(256) k_init(const T* __restrict__ rho, const T
   coefficients<L, N, R>(h, R(a.omega1), C);
   R f[L::Q];
   reconstruct<L, N, R>(C, f);
-  sfor<0, L::Q>([&](auto I) { dst[int64_t(I) * a.stride + n] = to_store<S, R>(f[I]); });
+  const int64_t off = node_offset(a, uint32_t(n));
+  sfor<0, L::Q>([&](auto I) { dst[int64_t(I) * a.si + off] = to_store<S, R>(f[I]); });
 }
 
 // ---------------------------------------------------------------------------
@@ -118,7 +143,8 @@ __global__ void __launch_bounds__(256) k_moments(const S* __restrict__ src, T* _
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= nodes) return;
   R f[L::Q];
-  sfor<0, L::Q>([&](auto I) { f[I] = R(src[int64_t(I) * a.stride + n]); });
+  const int64_t off = node_offset(a, uint32_t(n));
+  sfor<0, L::Q>([&](auto I) { f[I] = R(src[int64_t(I) * a.si + off]); });
   const Moments<R> m = raw_moments<L, R>(f);
   const Hydro<R> h = hydro<L, R>(m, R(a.rho0));
   if (rho) rho[n] = T(double(a.rho0) + double(h.drho));
@@ -180,7 +206,8 @@ __global__ void __launch_bounds__(kReduceBlock) k_totals(const S* __restrict__ s
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t n = begin + threadIdx.x; n < end; n += kReduceBlock) {
     double f[L::Q];
-    sfor<0, L::Q>([&](auto I) { f[I] = double(src[int64_t(I) * a.stride + n]); });
+    const int64_t off = node_offset(a, uint32_t(n));
+    sfor<0, L::Q>([&](auto I) { f[I] = double(src[int64_t(I) * a.si + off]); });
     const Moments<double> m = raw_moments<L, double>(f);
     const double rho = a.rho0 + m.d0;
     acc[0] += rho;
@@ -214,7 +241,8 @@ __global__ void __launch_bounds__(256) k_velocity(const S* __restrict__ src, dou
   const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (n >= nodes) return;
   double f[L::Q];
-  sfor<0, L::Q>([&](auto I) { f[I] = double(src[int64_t(I) * a.stride + n]); });
+  const int64_t off = node_offset(a, uint32_t(n));
+  sfor<0, L::Q>([&](auto I) { f[I] = double(src[int64_t(I) * a.si + off]); });
   const Moments<double> m = raw_moments<L, double>(f);
   const double inv = 1.0 / (a.rho0 + m.d0);
   u[n] = m.jx * inv;
@@ -275,6 +303,14 @@ hipError_t launch_velocity(const void* src, double* u, const StepArgs& a, hipStr
   const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
   hipLaunchKernelGGL((k_velocity<L, S>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s,
                      static_cast<const S*>(src), u, a);
+  return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_repack(const void* src, void* dst, bool to_compact, const StepArgs& a, hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  hipLaunchKernelGGL((k_repack<L, S>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const S*>(src), static_cast<S*>(dst), a, to_compact);
   return hipGetLastError();
 }
 
@@ -349,8 +385,17 @@ struct OpsImpl {
     }
     return hipErrorInvalidValue;
   }
+  static hipError_t repack(int storage, const void* src, void* dst, bool to_compact, const StepArgs& a,
+                           hipStream_t s) {
+    switch (storage) {
+      case 0: return launch_repack<L, double>(src, dst, to_compact, a, s);
+      case 1: return launch_repack<L, float>(src, dst, to_compact, a, s);
+      case 2: return launch_repack<L, _Float16>(src, dst, to_compact, a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   static const LatticeOps& table() {
-    static const LatticeOps t = {L::Q, L::D, L::NMAX, &step, &init, &moments, &totals, &velocity};
+    static const LatticeOps t = {L::Q, L::D, L::NMAX, &step, &init, &moments, &totals, &velocity, &repack};
     return t;
   }
 };

@@ -10,12 +10,14 @@ namespace lbrr {
 
 constexpr int kReduceBlock = 256;
 
-// Launch parameters shared by the kernels.
+// Launch parameters shared by the kernels.  Population i of node (x, y, z)
+// lives at element i*si + z*sz + y*sy + x of a buffer; the host picks the
+// strides (layout) and checks that every index stays inside the allocation.
 struct StepArgs {
   int nx, ny, nz;
-  int64_t stride;   // elements between consecutive population planes
-  double rho0;      // reference density of the deviation storage
-  double omega1;    // 1 - 1/tau
+  int64_t si, sy, sz;  // element strides of population, row and plane
+  double rho0;         // reference density of the deviation storage
+  double omega1;       // 1 - 1/tau
 };
 
 struct LatticeOps {
@@ -28,6 +30,8 @@ struct LatticeOps {
   hipError_t (*totals)(int storage, const void* src, double* partials, int nblocks, double* out, const StepArgs& a,
                        hipStream_t s);
   hipError_t (*velocity)(int storage, const void* src, double* u, const StepArgs& a, hipStream_t s);
+  // copy between the internal layout and compact SoA [q][nz][ny][nx] (to_compact: internal -> compact)
+  hipError_t (*repack)(int storage, const void* src, void* dst, bool to_compact, const StepArgs& a, hipStream_t s);
 };
 
 const LatticeOps& ops_d2q9();

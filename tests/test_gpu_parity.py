@@ -233,3 +233,20 @@ def test_full_size_d3q27_sampled_parity(lbrr, gpu, storage):
     e_u = np.abs(u_gpu[(slice(None),) + idx] - u_ref).max() / np.abs(u_ref).max()
     print(f"  sampled err rho {e_r:.2e} u {e_u:.2e}", flush=True)
     assert e_r <= tol and e_u <= tol
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("lat", ["D2Q9", "D3Q27"])
+def test_row_widths_and_wrap(lbrr, gpu, lat, storage):
+    """Every x-row width class of the step kernel: one lane, sub-wave rows, rows ending mid-wave,
+    exactly one wave (256 nodes at 4 per lane), several waves and blocks, widths not divisible by
+    the vector width (scalar path)."""
+    L = OL.lattice(lat)
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 5e-3}[storage]
+    for nx in (1, 2, 3, 4, 6, 8, 12, 64, 252, 256, 260, 516, 1030):
+        shape = (1, 5, nx) if L.D == 2 else (3, 4, nx)
+        print(f"width {lat} {storage} nx={nx}", flush=True)
+        ref = oracle_run(lat, 4, 0.66, shape, 3, 300 + nx)
+        got = gpu_run(lbrr, lat, 4, 0.66, shape, 3, 300 + nx, storage)
+        e = max(rel_l2(got[0], ref[0]), rel_linf(got[0], ref[0]), rel_l2(got[1], ref[1]), rel_linf(got[1], ref[1]))
+        assert e <= tol, (nx, e)
