@@ -161,6 +161,46 @@ def summarize_prof(paths):
     return "\n".join(lines)
 
 
+def write_traffic(fetch_dir, write_dir, out_path):
+    """HBM bytes per launch of the step kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of --probe.
+
+    Counters are in KiB per dispatch; each is scaled by what it reads for the
+    probe's plain copy of known size (1 GiB read + 1 GiB written).
+    """
+    import csv
+    import glob
+
+    def load(d, counter):
+        acc = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_kib = (1 << 30) / 1024.0
+    kf = [k for k in fetch if "k_copy" in k][0]
+    ff, fw = copy_kib / fetch[kf], copy_kib / write[kf]
+    nodes = 256**3
+    out = {"source_hash": kernel_source_hash(), "copy_calibration": {"fetch_factor": ff, "write_factor": fw},
+           "workload": "D3Q27 order 4, 256^3, one step launch"}
+    tags = {"fp32": "float", "fp16": "DF16_", "fp64": "double"}
+    for st, tag in tags.items():
+        ks = [k for k in fetch if "k_step" in k and "D3Q27" in k and tag in k]
+        if not ks:
+            continue
+        k = ks[0]
+        b = (fetch[k] * ff + write[k] * fw) * 1024.0
+        alg = {"fp32": 216, "fp16": 108, "fp64": 432}[st] * nodes
+        out[st] = {"kernel": k, "fetch_kib": fetch[k], "write_kib": write[k], "bytes_per_launch": round(b),
+                   "algorithmic_bytes": alg, "ratio": round(b / alg, 5)}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def cpu_baseline(cfg, budget_s=12.0):
     """The FP64 oracle on a 32^3 box of the same flow (same Re, Ma), single BLAS thread."""
     import numpy as np
@@ -201,9 +241,14 @@ def main(argv=None):
     ap.add_argument("--storages", default="fp32,fp16,fp64")
     ap.add_argument("--probe", action="store_true", help="short launch sequence for rocprofv3 counter runs")
     ap.add_argument("--summarize-prof", nargs="+", metavar="DIR", help="summarise rocprofv3 CSV output and exit")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the HBM traffic summary of the step kernels from two --pmc runs of --probe")
     a = ap.parse_args(argv)
     if a.summarize_prof:
         print(summarize_prof(a.summarize_prof))
+        return 0
+    if a.write_traffic:
+        print(json.dumps(write_traffic(*a.write_traffic, TRAFFIC_FILE), indent=1))
         return 0
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

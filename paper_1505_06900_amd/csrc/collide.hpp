@@ -161,7 +161,14 @@ __device__ __forceinline__ Hydro<R> hydro(const Moments<R>& m, R rho0) {
   Hydro<R> h;
   h.drho = m.d0;
   h.rho = rho0 + m.d0;
-  const R inv = R(1) / h.rho;
+  // 1/rho from the rounded sum rho0 + drho and its exact rounding error
+  // (two-sum), corrected to first order: rounding rho to the storage
+  // precision would otherwise bias u = j/rho by up to half an ulp of rho0 at
+  // every step, an error that accumulates in time.
+  const R bb = h.rho - rho0;
+  const R err = (rho0 - (h.rho - bb)) + (m.d0 - bb);
+  R inv = R(1) / h.rho;
+  inv = inv - inv * inv * err;
   h.jx = m.jx;
   h.jy = m.jy;
   h.ux = m.jx * inv;
