@@ -146,6 +146,76 @@ void lb_destroy(lb_handle h);
 /* Thread-local description of the last error ("" if none). */
 const char* lb_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Learned closure of a1^(2) on coarse D2Q9 runs.  Not part of the paper: a
+ * per-node MLP (36 -> 64 -> 64 -> 3, exact-erf GELU, BF16 matrix-core
+ * operands with FP32 accumulation) predicts a correction that is added to
+ * the pre-collision a1^(2) (P^(1) of Sec. 2) before the recursion of
+ * Sec. 3.1 (Eq. rel_a1) builds the higher orders and Eq. discr_bgk_reg
+ * reconstructs the populations.
+ *
+ * Parameter vector: LB_MLP_NPARAM FP32 values, in order W1 (64 x 36, row =
+ * output), b1 (64), W2 (64 x 64), b2 (64), W3 (3 x 64), b3 (3).
+ * Normalisation vector: LB_MLP_NNORM FP32 values: feature mean (36), feature
+ * std (36, > 0), output mean (3), output std (3, > 0); the network maps
+ * (x - mean)/std to (y - mean)/std.
+ * Features of a node for the step from a stored state g (36 FP32): the 9
+ * pulled pre-collision deviations f_i - w_i rho0, f_i(x) = g_i(x - xi_i), then
+ * for the neighbours x + (dx, dy), dy = -1, 0, 1 (outer), dx = -1, 0, 1
+ * (inner): rho - rho0, u_x, u_y of g.  Outputs: corrections of a1^(2)
+ * (xx, xy, yy).
+ * All pointers of these entry points are device pointers.  The MLP entry
+ * points share one library-owned workspace per process: calls that overlap
+ * on one device race.
+ */
+#define LB_MLP_NPARAM 6723
+#define LB_MLP_NNORM 78
+#define LB_MLP_NIN 36
+
+/* Enable (enable = 1) or disable the closure for lb_step of a D2Q9 handle
+ * (LB_ERR_UNSUPPORTED otherwise).  params / norm are copied (stream-ordered);
+ * with the closure on, each step first writes (rho - rho0, u) of the stored
+ * state to a handle-owned buffer, then runs the fused step with the MLP. */
+int lb_set_closure(lb_handle h, const float* params, const float* norm, int enable);
+
+/* Features (nodes x 36, row-major) of the step that would follow the current
+ * state, and labels (nodes x 3) = a_target - plain_weight * (a1^(2) of the
+ * pulled populations); a_target is packed [3][ny][nx] FP64 or NULL (read as
+ * 0).  D2Q9 only; the state is not advanced; asynchronous on the stream. */
+int lb_closure_features(lb_handle h, const double* a_target, double plain_weight, float* features, float* labels);
+
+/* Coarse-grain fine D2Q9 fields by factor x factor box averages (acoustic
+ * scaling, velocities and stresses keep their lattice-unit values):
+ *   rho_c = box(rho), u_c = box(rho u) / rho_c,
+ *   pi1_c = alpha box(pi1) + beta (box(rho u u) - rho_c u_c u_c),
+ * the second term being the sub-filter stress.  Inputs: rho [nfy][nfx],
+ * u [2][nfy][nfx], pi1 [3][nfy][nfx] (packed xx, xy, yy) of element type
+ * dtype; outputs FP64, [nfy/f][nfx/f] per component.  nfx, nfy multiples of
+ * factor. */
+int lb_closure_coarsen(const void* rho, const void* u, const void* pi1, int dtype, int nfx, int nfy, int factor,
+                       double alpha, double beta, double* rho_c, double* u_c, double* pi1_c, void* hip_stream);
+
+/* MLP outputs y (n x 3, de-normalised) for raw features x (n x 36). */
+int lb_mlp_forward(const float* params, const float* norm, const float* x, long long n, float* y, void* hip_stream);
+
+/* Gradient (LB_MLP_NPARAM) of the mean squared error of normalised outputs
+ * over the batch rows idx[0..batch) of x (raw features, n x 36) and t (raw
+ * targets, n x 3), and the loss itself (loss may be NULL).  Row indices
+ * outside [0, n) are clamped.  Per-block partial sums reduced in a fixed
+ * order: bitwise reproducible. */
+int lb_mlp_gradient(const float* params, const float* norm, const float* x, const float* t, long long n,
+                    const int* idx, int batch, float* grad, float* loss, void* hip_stream);
+
+/* Column mean and standard deviation (population form, FP64 accumulation in a
+ * fixed order) of x (n x dim, row-major), e.g. for the normalisation vector;
+ * a zero deviation is reported as 1. */
+int lb_column_stats(const float* x, long long n, int dim, float* mean, float* std, void* hip_stream);
+
+/* One bias-corrected Adam update of params (FP32 master copy) with moments m,
+ * v; step counts from 1. */
+int lb_mlp_adam(float* params, float* m, float* v, const float* grad, long long step, float lr, float beta1,
+                float beta2, float eps, void* hip_stream);
+
 /* Plain device copy of n bytes (n a multiple of 16, 16-byte aligned
  * pointers) on hip_stream: the bandwidth probe and hardware-counter
  * calibration kernel. */

@@ -7,8 +7,8 @@ Python side of the HIP library ``liblbrr.so`` (C ABI in include/lbrr.h):
 * ``Simulation``: a thin object over one handle that passes torch tensors'
   device pointers and torch's current HIP stream.  PyTorch provides device
   memory and streams only; every step of the update runs in the library's
-  kernels.  There is no CPU fallback: importing this package fails if the
-  library has not been built.
+  kernels.  There is no CPU fallback: the first use of any entry point
+  raises if the library has not been built.
 """
 from __future__ import annotations
 
@@ -19,25 +19,23 @@ from ._lib import (LB_D2Q9, LB_D3Q19, LB_D3Q27, LB_ERR_HIP, LB_ERR_INVALID_ARG, 
                    LB_ERR_UNSTABLE, LB_ERR_UNSUPPORTED, LB_F32, LB_F64, LB_OK, LB_STORE_FP16, LB_STORE_FP32,
                    LB_STORE_FP64, LBError)
 
-_L = _lib.load()
 
-# C entry points, same names as in include/lbrr.h
-lb_create = _L.lb_create
-lb_config = _L.lb_config
-lb_set_stream = _L.lb_set_stream
-lb_init_fields = _L.lb_init_fields
-lb_step = _L.lb_step
-lb_set_check_interval = _L.lb_set_check_interval
-lb_moments = _L.lb_moments
-lb_reduce = _L.lb_reduce
-lb_enstrophy = _L.lb_enstrophy
-lb_get_populations = _L.lb_get_populations
-lb_set_populations = _L.lb_set_populations
-lb_step_count = _L.lb_step_count
-lb_bytes_per_update = _L.lb_bytes_per_update
-lb_destroy = _L.lb_destroy
-lb_last_error = _L.lb_last_error
-lb_probe_copy = _L.lb_probe_copy
+def __getattr__(name):
+    """C entry points under their own names (``lb_create``, ...), loaded on first use.
+
+    The library is loaded lazily so that ``paper_1505_06900_amd.build`` can run
+    (and rebuild it) without loading a stale or missing ``liblbrr.so``."""
+    if name in _lib.SIGNATURES:
+        return getattr(_lib.load(), name)
+    if name in ("LB_MLP_NPARAM", "LB_MLP_NNORM", "LB_MLP_NIN"):
+        return getattr(_lib, name)
+    raise AttributeError(name)
+
+
+def load():
+    """Load liblbrr.so now (raises if it is missing or lacks a declared symbol)."""
+    return _lib.load()
+
 
 LATTICES = {"D2Q9": LB_D2Q9, "D3Q19": LB_D3Q19, "D3Q27": LB_D3Q27}
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
@@ -71,12 +69,12 @@ class Simulation:
         self.tau = tau
         self.order = order
         self.storage = storage
-        self.handle = lb_create(LATTICES[lattice], self.nx, self.ny, self.nz, float(tau), int(order))
+        self.handle = _lib.load().lb_create(LATTICES[lattice], self.nx, self.ny, self.nz, float(tau), int(order))
         if not self.handle:
             raise LBError(LB_ERR_INVALID_ARG, _lib.last_error())
-        check(lb_config(self.handle, STORAGE[storage], float(rho0)))
+        check(_lib.load().lb_config(self.handle, STORAGE[storage], float(rho0)))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        check(lb_set_stream(self.handle, ctypes.c_void_p(self.stream.cuda_stream)))
+        check(_lib.load().lb_set_stream(self.handle, ctypes.c_void_p(self.stream.cuda_stream)))
 
     # -- helpers ---------------------------------------------------------
     def _dev(self, t, dtype):
@@ -100,16 +98,16 @@ class Simulation:
         v = self._dev(u, dtype).reshape((self.d,) + self.shape)
         p = None if pi1 is None else self._dev(pi1, dtype).reshape((self.d * (self.d + 1) // 2,) + self.shape)
         code = LB_F64 if dtype == torch.float64 else LB_F32
-        check(lb_init_fields(self.handle, r.data_ptr(), v.data_ptr(), 0 if p is None else p.data_ptr(), code, 1))
+        check(_lib.load().lb_init_fields(self.handle, r.data_ptr(), v.data_ptr(), 0 if p is None else p.data_ptr(), code, 1))
         self._keep = (r, v, p)  # alive until the stream has consumed them
         return self
 
     def step(self, n=1):
-        check(lb_step(self.handle, int(n)))
+        check(_lib.load().lb_step(self.handle, int(n)))
         return self
 
     def set_check_interval(self, k):
-        check(lb_set_check_interval(self.handle, int(k)))
+        check(_lib.load().lb_set_check_interval(self.handle, int(k)))
 
     def moments(self, dtype=None, pi1=False):
         torch = _torch()
@@ -118,43 +116,67 @@ class Simulation:
         u = torch.empty((self.d,) + self.shape, device="cuda", dtype=dtype)
         p = torch.empty((self.d * (self.d + 1) // 2,) + self.shape, device="cuda", dtype=dtype) if pi1 else None
         code = LB_F64 if dtype == torch.float64 else LB_F32
-        check(lb_moments(self.handle, rho.data_ptr(), u.data_ptr(), 0 if p is None else p.data_ptr(), code, 1))
+        check(_lib.load().lb_moments(self.handle, rho.data_ptr(), u.data_ptr(), 0 if p is None else p.data_ptr(), code, 1))
         return (rho, u, p) if pi1 else (rho, u)
 
     def reduce(self):
         out = (ctypes.c_double * 5)()
-        check(lb_reduce(self.handle, out))
+        check(_lib.load().lb_reduce(self.handle, out))
         return tuple(out)
 
     def enstrophy(self):
         out = ctypes.c_double()
-        check(lb_enstrophy(self.handle, ctypes.byref(out)))
+        check(_lib.load().lb_enstrophy(self.handle, ctypes.byref(out)))
         return out.value
 
     def get_populations(self):
         torch = _torch()
         t = torch.empty((self.q,) + self.shape, device="cuda", dtype=self.storage_dtype)
-        check(lb_get_populations(self.handle, t.data_ptr(), 1))
+        check(_lib.load().lb_get_populations(self.handle, t.data_ptr(), 1))
         return t
 
     def set_populations(self, t):
         torch = _torch()
         t = torch.as_tensor(t).to(device="cuda", dtype=self.storage_dtype).contiguous()
         assert tuple(t.shape) == (self.q,) + self.shape
-        check(lb_set_populations(self.handle, t.data_ptr(), 1))
+        check(_lib.load().lb_set_populations(self.handle, t.data_ptr(), 1))
         self._keep = (t,)
+
+    def set_closure(self, params=None, norm=None, enable=True):
+        """Enable the learned a1^(2) closure (D2Q9) with FP32 params (6723) and norm (78) tensors."""
+        torch = _torch()
+        if not enable:
+            check(_lib.load().lb_set_closure(self.handle, None, None, 0))
+            return
+        p = torch.as_tensor(params).to(device="cuda", dtype=torch.float32).contiguous()
+        n = torch.as_tensor(norm).to(device="cuda", dtype=torch.float32).contiguous()
+        check(_lib.load().lb_set_closure(self.handle, p.data_ptr(), n.data_ptr(), 1))
+        self._keep_closure = (p, n)
+
+    def closure_features(self, a_target=None, plain_weight=1.0):
+        """(features [nodes, 36], labels [nodes, 3]) of the next step;
+        labels = a_target - plain_weight * plain a1^(2)."""
+        torch = _torch()
+        nodes = self.nx * self.ny * self.nz
+        feat = torch.empty((nodes, 36), device="cuda", dtype=torch.float32)
+        lab = torch.empty((nodes, 3), device="cuda", dtype=torch.float32)
+        at = None if a_target is None else torch.as_tensor(a_target).to(device="cuda", dtype=torch.float64).contiguous()
+        check(_lib.load().lb_closure_features(self.handle, 0 if at is None else at.data_ptr(), float(plain_weight),
+                                              feat.data_ptr(), lab.data_ptr()))
+        self._keep_target = at
+        return feat, lab
 
     @property
     def steps(self):
-        return lb_step_count(self.handle)
+        return _lib.load().lb_step_count(self.handle)
 
     @property
     def bytes_per_update(self):
-        return lb_bytes_per_update(self.handle)
+        return _lib.load().lb_bytes_per_update(self.handle)
 
     def close(self):
         if getattr(self, "handle", None):
-            lb_destroy(self.handle)
+            _lib.load().lb_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

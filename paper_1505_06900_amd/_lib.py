@@ -21,6 +21,7 @@ LB_ERR_OOM = -3
 LB_ERR_HIP = -4
 LB_ERR_UNSTABLE = -5
 LB_ERR_STATE = -6
+LB_MLP_NPARAM, LB_MLP_NNORM, LB_MLP_NIN = 6723, 78, 36
 
 # name -> (restype, argtypes), exactly the declarations of include/lbrr.h
 _VP, _I, _D, _LL, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong, ctypes.c_size_t
@@ -41,6 +42,14 @@ SIGNATURES = {
     "lb_destroy": (None, [_VP]),
     "lb_last_error": (ctypes.c_char_p, []),
     "lb_probe_copy": (_I, [_VP, _VP, _SZ, _VP]),
+    "lb_set_closure": (_I, [_VP, _VP, _VP, _I]),
+    "lb_closure_features": (_I, [_VP, _VP, _D, _VP, _VP]),
+    "lb_closure_coarsen": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _D, _D, _VP, _VP, _VP, _VP]),
+    "lb_mlp_forward": (_I, [_VP, _VP, _VP, _LL, _VP, _VP]),
+    "lb_mlp_gradient": (_I, [_VP, _VP, _VP, _VP, _LL, _VP, _I, _VP, _VP, _VP]),
+    "lb_column_stats": (_I, [_VP, _LL, _I, _VP, _VP, _VP]),
+    "lb_mlp_adam": (_I, [_VP, _VP, _VP, _VP, _LL, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                         _VP]),
 }
 
 _lib = None

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblbrr.so")
 
-SOURCES = ["api.hip", "diag.hip", "kernels_d2q9.hip", "kernels_d3q19.hip", "kernels_d3q27.hip"]
+SOURCES = ["api.hip", "diag.hip", "closure.hip", "kernels_d2q9.hip", "kernels_d3q19.hip", "kernels_d3q27.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 
+#include "closure.hpp"
 #include "lbrr.h"
 #include "ops.hpp"
 
@@ -77,6 +78,12 @@ struct lb_ctx {
   int nblocks = 0;
   double* dev_out = nullptr;
   double* vel = nullptr;
+  // learned closure (D2Q9)
+  bool closure_on = false;
+  float* cl_params = nullptr;   // kMlpNParam
+  float* cl_norm = nullptr;     // kMlpNNorm
+  uint16_t* cl_packed = nullptr;
+  float* cl_m = nullptr;        // 3 * nodes: rho - rho0, u_x, u_y of the stored state
 
   int64_t nodes() const { return int64_t(nx) * ny * nz; }
   int q() const { return ops->q; }
@@ -105,6 +112,16 @@ struct lb_ctx {
     dev_out = nullptr;
     vel = nullptr;
     ready = false;
+  }
+  void release_closure() {
+    for (void* p : {static_cast<void*>(cl_params), static_cast<void*>(cl_norm), static_cast<void*>(cl_packed),
+                    static_cast<void*>(cl_m)})
+      if (p) (void)hipFree(p);
+    cl_params = nullptr;
+    cl_norm = nullptr;
+    cl_packed = nullptr;
+    cl_m = nullptr;
+    closure_on = false;
   }
 };
 
@@ -316,7 +333,10 @@ int lb_step(lb_handle h, long long n) {
   if (!h->ready) return fail(LB_ERR_STATE, "lb_step before lb_init_fields / lb_set_populations");
   const StepArgs a = h->args();
   for (long long k = 0; k < n; ++k) {
-    hipError_t e = h->ops->step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->stream);
+    hipError_t e = h->closure_on
+                       ? lbrr::closure_step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], h->cl_m, a,
+                                            h->cl_packed, h->cl_params, h->cl_norm, h->stream)
+                       : h->ops->step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     h->cur ^= 1;
     ++h->steps;
@@ -438,7 +458,145 @@ void lb_destroy(lb_handle h) {
   (void)hipSetDevice(h->device);
   if (h->buf[0]) (void)hipStreamSynchronize(h->stream);
   h->release();
+  h->release_closure();
   delete h;
+}
+
+// ---------------------------------------------------------------------------
+// Learned closure (D2Q9).
+
+namespace {
+
+// Reusable device workspace of the MLP entry points (grown on demand; calls
+// that overlap on one device must not share it).
+struct Workspace {
+  void* ptr = nullptr;
+  size_t size = 0;
+  int device = -1;
+};
+Workspace g_ws;
+
+int workspace(size_t bytes, void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (g_ws.ptr && (g_ws.size < bytes || g_ws.device != dev)) {
+    int cur = dev;
+    (void)hipSetDevice(g_ws.device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(g_ws.ptr);
+    (void)hipSetDevice(cur);
+    g_ws.ptr = nullptr;
+  }
+  if (!g_ws.ptr) {
+    const size_t sz = bytes < (size_t(1) << 20) ? (size_t(1) << 20) : bytes;
+    HIP_TRY(hipMalloc(&g_ws.ptr, sz), "hipMalloc MLP workspace");
+    g_ws.size = sz;
+    g_ws.device = dev;
+  }
+  *out = g_ws.ptr;
+  return LB_OK;
+}
+
+}  // namespace
+
+int lb_set_closure(lb_handle h, const float* params, const float* norm, int enable) {
+  if (int r = check_handle(h)) return r;
+  if (h->lattice != LB_D2Q9) return fail(LB_ERR_UNSUPPORTED, "the learned closure is implemented for D2Q9 only");
+  if (!enable) {
+    h->closure_on = false;
+    return LB_OK;
+  }
+  if (!params || !norm) return fail(LB_ERR_INVALID_ARG, "params and norm must not be NULL");
+  if (!h->cl_params) {
+    HIP_TRY(hipMalloc(&h->cl_params, sizeof(float) * lbrr::kMlpNParam), "hipMalloc closure params");
+    HIP_TRY(hipMalloc(&h->cl_norm, sizeof(float) * lbrr::kMlpNNorm), "hipMalloc closure norm");
+    HIP_TRY(hipMalloc(&h->cl_packed, sizeof(uint16_t) * lbrr::kMlpNPacked), "hipMalloc closure weights");
+    HIP_TRY(hipMalloc(&h->cl_m, sizeof(float) * 3 * size_t(h->nodes())), "hipMalloc closure moments");
+  }
+  HIP_TRY(hipMemcpyAsync(h->cl_params, params, sizeof(float) * lbrr::kMlpNParam, hipMemcpyDeviceToDevice, h->stream),
+          "copy closure params");
+  HIP_TRY(hipMemcpyAsync(h->cl_norm, norm, sizeof(float) * lbrr::kMlpNNorm, hipMemcpyDeviceToDevice, h->stream),
+          "copy closure norm");
+  hipError_t e = lbrr::mlp_pack(h->cl_params, h->cl_packed, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "pack closure weights");
+  h->closure_on = true;
+  return LB_OK;
+}
+
+int lb_closure_features(lb_handle h, const double* a_target, double plain_weight, float* features, float* labels) {
+  if (int r = check_handle(h)) return r;
+  if (h->lattice != LB_D2Q9) return fail(LB_ERR_UNSUPPORTED, "the learned closure is implemented for D2Q9 only");
+  if (!features || !labels) return fail(LB_ERR_INVALID_ARG, "features and labels must not be NULL");
+  if (!h->ready) return fail(LB_ERR_STATE, "no state");
+  void* m = nullptr;
+  if (int r = workspace(sizeof(float) * 3 * size_t(h->nodes()), &m)) return r;
+  hipError_t e = lbrr::closure_features(h->storage, h->buf[h->cur], static_cast<float*>(m), h->args(), a_target,
+                                        plain_weight, features, labels, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "closure features");
+  return LB_OK;
+}
+
+int lb_closure_coarsen(const void* rho, const void* u, const void* pi1, int dtype, int nfx, int nfy, int factor,
+                       double alpha, double beta, double* rho_c, double* u_c, double* pi1_c, void* hip_stream) {
+  if (!rho || !u || !pi1 || !rho_c || !u_c || !pi1_c) return fail(LB_ERR_INVALID_ARG, "NULL pointer");
+  if (dtype != LB_F64 && dtype != LB_F32) return fail(LB_ERR_INVALID_ARG, "bad dtype %d", dtype);
+  if (factor < 1 || nfx < factor || nfy < factor || nfx % factor || nfy % factor)
+    return fail(LB_ERR_INVALID_ARG, "fine dims must be positive multiples of the factor");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(LB_ERR_INVALID_ARG, "alpha, beta must be finite");
+  hipError_t e = lbrr::closure_coarsen(dtype, rho, u, pi1, nfx, nfy, factor, alpha, beta, rho_c, u_c, pi1_c,
+                                       static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "coarsen kernel");
+  return LB_OK;
+}
+
+int lb_mlp_forward(const float* params, const float* norm, const float* x, long long n, float* y, void* hip_stream) {
+  if (!params || !norm || (n > 0 && (!x || !y))) return fail(LB_ERR_INVALID_ARG, "NULL pointer");
+  if (n < 0) return fail(LB_ERR_INVALID_ARG, "n must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  void* ws = nullptr;
+  if (int r = workspace(sizeof(uint16_t) * lbrr::kMlpNPacked, &ws)) return r;
+  uint16_t* packed = static_cast<uint16_t*>(ws);
+  hipError_t e = lbrr::mlp_pack(params, packed, s);
+  if (e == hipSuccess) e = lbrr::mlp_infer(x, n, packed, params, norm, y, s);
+  if (e != hipSuccess) return hip_fail(e, "MLP forward");
+  return LB_OK;
+}
+
+int lb_mlp_gradient(const float* params, const float* norm, const float* x, const float* t, long long n,
+                    const int* idx, int batch, float* grad, float* loss, void* hip_stream) {
+  if (!params || !norm || !x || !t || !idx || !grad) return fail(LB_ERR_INVALID_ARG, "NULL pointer");
+  if (batch < 1 || n < 1) return fail(LB_ERR_INVALID_ARG, "batch and n must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int nb = lbrr::mlp_train_blocks(batch);
+  const size_t packed_bytes = sizeof(uint16_t) * lbrr::kMlpNPacked;
+  const size_t part_bytes = sizeof(float) * size_t(nb) * lbrr::kMlpNParam;
+  void* ws = nullptr;
+  if (int r = workspace(packed_bytes + part_bytes + sizeof(float) * size_t(nb) + 256, &ws)) return r;
+  char* base = static_cast<char*>(ws);
+  uint16_t* packed = reinterpret_cast<uint16_t*>(base);
+  float* gpart = reinterpret_cast<float*>(base + packed_bytes);
+  float* lpart = reinterpret_cast<float*>(base + packed_bytes + part_bytes);
+  hipError_t e = lbrr::mlp_pack(params, packed, s);
+  if (e == hipSuccess) e = lbrr::mlp_gradient(x, t, n, idx, batch, packed, params, norm, gpart, lpart, grad, loss, s);
+  if (e != hipSuccess) return hip_fail(e, "MLP gradient");
+  return LB_OK;
+}
+
+int lb_column_stats(const float* x, long long n, int dim, float* mean, float* std, void* hip_stream) {
+  if (!x || !mean || !std) return fail(LB_ERR_INVALID_ARG, "NULL pointer");
+  if (n < 1 || dim < 1) return fail(LB_ERR_INVALID_ARG, "n and dim must be >= 1");
+  hipError_t e = lbrr::column_stats(x, n, dim, mean, std, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "column stats kernel");
+  return LB_OK;
+}
+
+int lb_mlp_adam(float* params, float* m, float* v, const float* grad, long long step, float lr, float beta1,
+                float beta2, float eps, void* hip_stream) {
+  if (!params || !m || !v || !grad) return fail(LB_ERR_INVALID_ARG, "NULL pointer");
+  if (step < 1) return fail(LB_ERR_INVALID_ARG, "step counts from 1");
+  hipError_t e = lbrr::mlp_adam(params, m, v, grad, step, lr, beta1, beta2, eps, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "Adam kernel");
+  return LB_OK;
 }
 
 int lb_probe_copy(const void* src, void* dst, size_t n, void* hip_stream) {

@@ -1,0 +1,74 @@
+// Device building blocks of the learned a1^(2) closure MLP (36 -> 64 -> 64 -> 3,
+// GELU): BF16 operands on the matrix cores (v_mfma_f32_16x16x16_bf16), FP32
+// accumulation, LDS-resident tiles.  The closure is not part of the paper.
+//
+// Parameter vector (FP32, 6723 values): W1 (64 x 36, out x in), b1 (64),
+// W2 (64 x 64), b2 (64), W3 (3 x 64), b3 (3).  Normalisation vector (78):
+// x_mean (36), x_std (36), y_mean (3), y_std (3).
+// Packed BF16 weights (8192 values): W1 as 64 x 48 (in padded with zeros),
+// W2 as 64 x 64, W3 as 16 x 64 (outputs padded with zero rows).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbrr {
+namespace mlp {
+
+constexpr int kIn = 36, kInP = 48, kH = 64, kOut = 3, kOutP = 16;
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kH * kIn, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
+              kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kOut * kH, kNParam = kOffB3 + kOut;
+static_assert(kNParam == 6723, "parameter count");
+constexpr int kNNorm = 2 * kIn + 2 * kOut;
+constexpr int kPW1 = 0, kPW2 = kPW1 + kH * kInP, kPW3 = kPW2 + kH * kH, kNPacked = kPW3 + kOutP * kH;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __builtin_bit_cast(float, uint32_t(b) << 16); }
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// One 16 x 16 output tile of A (M x K) * B (K x N) from BF16 values in LDS:
+// A(i, k) = A[i * a_rs + k * a_cs], B(k, j) = B[k * b_rs + j * b_cs]; rows
+// i0..i0+15, columns j0..j0+15, K a multiple of 16.  Lane l of the wave holds
+// the results D[i0 + 4*(l/16) + r][j0 + l%16], r = 0..3 (matrix-core layout).
+template <int K>
+__device__ __forceinline__ f32x4 tile(const uint16_t* A, int a_rs, int a_cs, const uint16_t* B, int b_rs, int b_cs,
+                                      int i0, int j0, f32x4 acc) {
+  const int l = threadIdx.x & 63;
+  const int ii = i0 + (l & 15), jj = j0 + (l & 15), kk = 4 * (l >> 4);
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[r] = short(A[ii * a_rs + (k0 + kk + r) * a_cs]);
+      b[r] = short(B[(k0 + kk + r) * b_rs + jj * b_cs]);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Row and column of element r of a lane's tile result.
+__device__ __forceinline__ int tile_row(int i0, int r) { return i0 + 4 * ((threadIdx.x & 63) >> 4) + r; }
+__device__ __forceinline__ int tile_col(int j0) { return j0 + (threadIdx.x & 15); }
+
+// Load the packed BF16 weights (kNPacked values) into LDS with the whole block.
+__device__ __forceinline__ void load_weights(const uint16_t* __restrict__ packed, uint16_t* lds) {
+  for (int k = threadIdx.x; k < kNPacked; k += blockDim.x) lds[k] = packed[k];
+}
+
+}  // namespace mlp
+}  // namespace lbrr

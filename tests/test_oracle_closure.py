@@ -133,3 +133,23 @@ def test_features_match_brute_force_gather():
             axy = (pulled * L.c[:, 0] * L.c[:, 1]).sum() - r * ux * uy
             ayy = (pulled * L.c[:, 1] ** 2).sum() - r / 3 - r * uy * uy
             np.testing.assert_allclose(Ap[y * nx + x], [axx, axy, ayy], atol=1e-15)
+
+
+def test_flux_label_factor_from_the_steady_response():
+    """Iterate the a1^(2) recursion A <- A_s + omega (A + D) of a constant correction D and check that
+    the steady flux, half the sum of the pre- and post-collision moments, carries omega D/(1 - omega);
+    D = flux_label_factor(tau) * T then carries exactly T."""
+    for tau in (0.508868, 0.6, 0.9):
+        om = 1 - 1 / tau
+        A_s, T = 3e-4, 2e-6
+        D = OC.flux_label_factor(tau) * T
+        A = 0.0
+        for _ in range(5000):
+            A = A_s + om * (A + D)
+        flux_with = 0.5 * (A + om * (A + D))
+        A0 = 0.0
+        for _ in range(5000):
+            A0 = A_s + om * A0
+        flux_without = 0.5 * (A0 + om * A0)
+        assert flux_with - flux_without == pytest.approx(T, rel=1e-9)
+        assert flux_without == pytest.approx((1 - 0.5 / tau) * A0, rel=1e-12)
