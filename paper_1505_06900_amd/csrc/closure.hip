@@ -157,7 +157,7 @@ __device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uin
   for (int t = 0; t < 16; ++t) {
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kInP>(regA, kInP, 1, w + kPW1, 1, kInP, i0, j0, acc);
+    acc = tile_kc<kInP>(regA, kInP, w + kPW1, kInP, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) regB[tile_row(i0, r) * kH + j] = to_bf16(gelu(acc[r] + params[kOffB1 + j]));
   }
@@ -166,7 +166,7 @@ __device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uin
   for (int t = 0; t < 16; ++t) {
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kH>(regB, kH, 1, w + kPW2, 1, kH, i0, j0, acc);
+    acc = tile_kc<kH>(regB, kH, w + kPW2, kH, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) regA[tile_row(i0, r) * kH + j] = to_bf16(gelu(acc[r] + params[kOffB2 + j]));
   }
@@ -176,7 +176,7 @@ __device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uin
   for (int t = 0; t < 4; ++t) {
     const int i0 = 16 * t;
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kH>(regA, kH, 1, w + kPW3, 1, kH, i0, 0, acc);
+    acc = tile_kc<kH>(regA, kH, w + kPW3, kH, i0, 0, acc);
     const int j = tile_col(0);
     for (int r = 0; r < 4; ++r) ys[tile_row(i0, r) * kOutP + j] = acc[r] + (j < kOut ? params[kOffB3 + j] : 0.0f);
   }
@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(const float* __r
                                                                 const uint16_t* __restrict__ packed,
                                                                 const float* __restrict__ params,
                                                                 const float* __restrict__ norm, float* __restrict__ y) {
-  __shared__ uint16_t w[kNPacked];
-  __shared__ uint16_t reg[kInferWaves][2][64 * 64];
+  __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
+  __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][64 * 64];
   load_weights(packed, w);
   const int wave = threadIdx.x >> 6;
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -223,8 +223,11 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
                                                    const uint16_t* __restrict__ packed,
                                                    const float* __restrict__ params, const float* __restrict__ norm,
                                                    float* __restrict__ gpart, float* __restrict__ lpart) {
-  __shared__ uint16_t w[kNPacked];
-  __shared__ uint16_t xs[kTS * kInP], h1s[kTS * kH], h2s[kTS * kH], dys[kTS * kOutP], dz2s[kTS * kH], dz1s[kTS * kH];
+  __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[kTS * kInP];
+  __shared__ __attribute__((aligned(16))) uint16_t h1s[kTS * kH];
+  __shared__ __attribute__((aligned(16))) uint16_t h2s[kTS * kH];
+  __shared__ __attribute__((aligned(16))) uint16_t dys[kTS * kOutP], dz2s[kTS * kH], dz1s[kTS * kH];
   __shared__ float z1[kTS * kH], z2[kTS * kH], ys[kTS * kOutP], ts[kTS * kOut], red[kTS * kOut];
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int s0 = blockIdx.x * kTS;
@@ -246,7 +249,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   for (int t = wave; t < 8; t += nw) {  // layer 1: 2 x 4 tiles
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kInP>(xs, kInP, 1, w + kPW1, 1, kInP, i0, j0, acc);
+    acc = tile_kc<kInP>(xs, kInP, w + kPW1, kInP, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) {
       const int i = tile_row(i0, r);
@@ -259,7 +262,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   for (int t = wave; t < 8; t += nw) {  // layer 2
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kH>(h1s, kH, 1, w + kPW2, 1, kH, i0, j0, acc);
+    acc = tile_kc<kH>(h1s, kH, w + kPW2, kH, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) {
       const int i = tile_row(i0, r);
@@ -272,7 +275,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   for (int t = wave; t < 2; t += nw) {  // layer 3: 2 x 1 tiles
     const int i0 = 16 * t;
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kH>(h2s, kH, 1, w + kPW3, 1, kH, i0, 0, acc);
+    acc = tile_kc<kH>(h2s, kH, w + kPW3, kH, i0, 0, acc);
     const int j = tile_col(0);
     for (int r = 0; r < 4; ++r) ys[tile_row(i0, r) * kOutP + j] = acc[r] + (j < kOut ? params[kOffB3 + j] : 0.0f);
   }
@@ -454,8 +457,8 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_step_closure(const S* __re
                                                                    const float* __restrict__ params,
                                                                    const float* __restrict__ norm) {
   using R = typename Prec<S>::R;
-  __shared__ uint16_t w[kNPacked];
-  __shared__ uint16_t reg[kInferWaves][2][64 * 64];
+  __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
+  __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][64 * 64];
   load_weights(packed, w);
   const int xr = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = xr < a.nx;

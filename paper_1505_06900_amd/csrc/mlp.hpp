@@ -61,6 +61,20 @@ __device__ __forceinline__ f32x4 tile(const uint16_t* A, int a_rs, int a_cs, con
   return acc;
 }
 
+// Same tile when both operands are contiguous along k (A(i, k) = A[i * lda + k],
+// B(k, j) = B[j * ldb + k], lda and ldb multiples of 4, 8-byte aligned rows):
+// each lane fetches its four k values of A and of B with one 8-byte LDS read.
+template <int K>
+__device__ __forceinline__ f32x4 tile_kc(const uint16_t* A, int lda, const uint16_t* B, int ldb, int i0, int j0,
+                                         f32x4 acc) {
+  const int l = threadIdx.x & 63;
+  const bf16x4* ap = reinterpret_cast<const bf16x4*>(A + (i0 + (l & 15)) * lda + 4 * (l >> 4));
+  const bf16x4* bp = reinterpret_cast<const bf16x4*>(B + (j0 + (l & 15)) * ldb + 4 * (l >> 4));
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 16) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ap[k0 / 4], bp[k0 / 4], acc, 0, 0, 0);
+  return acc;
+}
+
 // Row and column of element r of a lane's tile result.
 __device__ __forceinline__ int tile_row(int i0, int r) { return i0 + 4 * ((threadIdx.x & 63) >> 4) + r; }
 __device__ __forceinline__ int tile_col(int j0) { return j0 + (threadIdx.x & 15); }

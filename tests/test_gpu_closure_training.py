@@ -33,7 +33,7 @@ def test_trained_closure_beats_plain_coarse_run(lbrr, gpu):
     norm = C.norm_stats(x, y)
     params, losses = C.train(x, y, norm, steps=3000, batch=4096, lr=1e-3, seed=0)
     print("losses", losses, flush=True)
-    assert losses[-1][1] < 0.2 * losses[0][1]
+    assert losses[-1][1] < 0.02  # normalised mean squared error (1 = predicting the mean)
     r2 = C.r2_score(C.predict(params, norm, xt), yt)
     print("held-out R2", r2, flush=True)
     assert np.all(r2 > 0.9)
