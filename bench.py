@@ -161,6 +161,50 @@ def summarize_prof(paths):
     return "\n".join(lines)
 
 
+def closure_run(log_fn=None):
+    """Learned a1^(2) closure on decaying 2D turbulence (fine 1024^2, coarse 256^2, D2Q9 order 4).
+
+    Trains on seeds 0-3 with the library's kernels and compares the closure run with the plain
+    coarse run against the coarse-grained fine run (held-out seed 4, 2000 coarse steps)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1505_06900_amd import closure as C
+
+    cf, cc = dict(W.WORKLOADS["turb2d_fine_1024"]), dict(W.WORKLOADS["turb2d_coarse_256"])
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    for seed in range(4):
+        x, y = C.generate(seed, cf, cc, snapshots=40, interval=200)
+        xs.append(x)
+        ys.append(y)
+    x, y = torch.cat(xs), torch.cat(ys)
+    del xs, ys
+    xt, yt = C.generate(4, cf, cc, snapshots=20, interval=200)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    norm = C.norm_stats(x, y)
+    t0 = time.perf_counter()
+    steps, batch = 3000, 4096
+    params, losses = C.train(x, y, norm, steps=steps, batch=batch, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    r2 = C.r2_score(C.predict(params, norm, xt), yt)
+    res = C.a_posteriori(params, norm, 4, cf, cc, coarse_steps=2000, every=200)
+    ep, ec = res["err_u"]["plain"], res["err_u"]["closure"]
+    return {
+        "workload": "decaying 2D turbulence, D2Q9 order 4, fine 1024^2 tau 0.535472, coarse 256^2 tau 0.508868",
+        "train_samples": int(x.shape[0]), "train_steps": steps, "batch": batch,
+        "train_s": round(t_train, 2), "datagen_s": round(t_gen, 2),
+        "mlp_train_tflops": round(6 * 6723 * batch * steps / t_train / 1e12, 3),
+        "final_loss": round(losses[-1][1], 5), "heldout_r2": [round(float(v), 4) for v in r2],
+        "u_err_vs_filtered_fine_at_2000": {"plain": round(ep[-1], 5), "closure": round(ec[-1], 5)},
+        "stable": res["stable"], "step_ms": {k: round(v, 4) for k, v in res["step_ms"].items()},
+        "cost_ratio": round(res.get("cost_ratio", float("nan")), 2),
+    }
+
+
 def write_traffic(fetch_dir, write_dir, out_path):
     """HBM bytes per launch of the step kernels from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of --probe.
 
@@ -238,6 +282,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure measurement")
     ap.add_argument("--storages", default="fp32,fp16,fp64")
     ap.add_argument("--probe", action="store_true", help="short launch sequence for rocprofv3 counter runs")
     ap.add_argument("--summarize-prof", nargs="+", metavar="DIR", help="summarise rocprofv3 CSV output and exit")
@@ -320,6 +365,10 @@ def main(argv=None):
     }
     out["copy_probe"] = copy_probe(P, torch)
     log(f"copy probe: {out['copy_probe']['gbs']} GB/s")
+    if not a.no_closure:
+        log("learned closure: data generation, training, a-posteriori comparison")
+        out["closure"] = closure_run()
+        log(f"closure: {out['closure']['u_err_vs_filtered_fine_at_2000']}")
     if not a.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(cfg)

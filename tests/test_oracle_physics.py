@@ -122,3 +122,28 @@ def test_taylor_green_kinetic_energy_decay():
     k2 = 2 * (2 * math.pi / n) ** 2
     assert slope == pytest.approx(2 * nu_of(tau) * k2, rel=0.01)
     assert ke[-1] / ke[0] == pytest.approx(math.exp(-2 * nu_of(tau) * k2 * 1000), rel=0.02)
+
+
+def advected_phase(U=0.1, n=32, steps=100):
+    """Phase drift of a transverse shear wave u_y = eps sin(k x) carried by a uniform flow U along x."""
+    k = 2 * math.pi / n
+    x = np.arange(n)
+    rho = np.ones((1, 2, n))
+    u = np.zeros((2, 1, 2, n))
+    u[0] = U
+    u[1] = 1e-3 * np.sin(k * x)
+    L = Lm.lattice("D2Q9")
+    f = rr.init_populations(L, 4, rho, u)
+    c0 = np.sum(u[1, 0, 0] * np.exp(-1j * k * x))
+    for _ in range(steps):
+        f = rr.step(L, 4, 0.8, f)
+    _, v, _ = rr.moments(L, f)
+    c1 = np.sum(v[1, 0, 0] * np.exp(-1j * k * x))
+    return float(np.angle(c1 / c0)), -k * U * steps
+
+
+def test_shear_wave_is_carried_with_the_flow():
+    """u_y(x, t) = eps e^(-nu k^2 t) sin(k (x - U t)): the Fourier phase drifts by -k U t, i.e. the
+    wave moves with the flow (streaming moves f_i along +xi_i)."""
+    got, expected = advected_phase()
+    assert got == pytest.approx(expected, abs=0.02)
