@@ -141,15 +141,16 @@ __global__ void __launch_bounds__(256) k_features(const S* __restrict__ src, con
 // ---------------------------------------------------------------------------
 // Forward pass of 64 samples per wave; every thread of the block calls it
 // (barriers inside).  feat: the lane's raw features; returns the lane's
-// de-normalised outputs.  LDS: weights (kNPacked BF16) shared by the block, two
-// 8 KiB regions per wave.
+// de-normalised outputs.  LDS: weights (kNPacked BF16) and 1/std of the
+// features shared by the block, two 8 KiB regions per wave.
 __device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uint16_t* w, uint16_t* regA,
                                              uint16_t* regB, const float* __restrict__ params,
-                                             const float* __restrict__ norm, float (&out)[kOut]) {
+                                             const float* __restrict__ norm, const float* inv_std,
+                                             float (&out)[kOut]) {
   const int lane = threadIdx.x & 63;
   // normalised BF16 features, row = lane, 48 columns (zero padded)
   for (int k = 0; k < kInP; ++k) {
-    const float v = (k < kIn) ? (feat[k] - norm[k]) / norm[kIn + k] : 0.0f;
+    const float v = (k < kIn) ? (feat[k] - norm[k]) * inv_std[k] : 0.0f;
     regA[lane * kInP + k] = to_bf16(v);
   }
   __syncthreads();
@@ -194,7 +195,9 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(const float* __r
                                                                 const float* __restrict__ norm, float* __restrict__ y) {
   __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
   __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][64 * 64];
+  __shared__ float inv_std[kIn];
   load_weights(packed, w);
+  if (threadIdx.x < kIn) inv_std[threadIdx.x] = 1.0f / norm[kIn + threadIdx.x];
   const int wave = threadIdx.x >> 6;
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t sc = s < n ? s : n - 1;  // every lane takes part in the matrix-core tiles
@@ -202,7 +205,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(const float* __r
   for (int k = 0; k < kIn; ++k) feat[k] = x[sc * kIn + k];
   __syncthreads();
   float out[kOut];
-  forward_wave(feat, w, reg[wave][0], reg[wave][1], params, norm, out);
+  forward_wave(feat, w, reg[wave][0], reg[wave][1], params, norm, inv_std, out);
   if (s < n)
     for (int c = 0; c < kOut; ++c) y[s * kOut + c] = out[c];
 }
@@ -370,15 +373,21 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   }
 }
 
-// grad[p] = sum over blocks of the partials (fixed order); loss = sum / (3 B).
+// grad[p] = sum over blocks of the partials in a fixed order (eight interleaved
+// accumulators keep eight loads in flight per thread); loss = sum / (3 B).
 __global__ void __launch_bounds__(256) k_grad_reduce(const float* __restrict__ gpart, const float* __restrict__ lpart,
                                                      int nblocks, int batch, float* __restrict__ grad,
                                                      float* __restrict__ loss) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < kNParam) {
-    float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += gpart[int64_t(b) * kNParam + p];
-    grad[p] = s;
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int b = 0;
+    for (; b + 8 <= nblocks; b += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += gpart[int64_t(b + u) * kNParam + p];
+    }
+    for (; b < nblocks; ++b) s[0] += gpart[int64_t(b) * kNParam + p];
+    grad[p] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   }
   if (p == 0 && loss) {
     float s = 0.0f;
@@ -459,7 +468,9 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_step_closure(const S* __re
   using R = typename Prec<S>::R;
   __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
   __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][64 * 64];
+  __shared__ float inv_std[kIn];
   load_weights(packed, w);
+  if (threadIdx.x < kIn) inv_std[threadIdx.x] = 1.0f / norm[kIn + threadIdx.x];
   const int xr = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = xr < a.nx;
   const int x = active ? xr : xr % a.nx;
@@ -470,7 +481,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_step_closure(const S* __re
   features36<R>(f, m, a, x, y, feat);
   __syncthreads();
   float d[kOut];
-  forward_wave(feat, w, reg[threadIdx.x >> 6][0], reg[threadIdx.x >> 6][1], params, norm, d);
+  forward_wave(feat, w, reg[threadIdx.x >> 6][0], reg[threadIdx.x >> 6][1], params, norm, inv_std, d);
   const Moments<R> mo = raw_moments<D2Q9, R>(f);
   Hydro<R> h = hydro<D2Q9, R>(mo, R(a.rho0));
   h.axx += R(d[0]);

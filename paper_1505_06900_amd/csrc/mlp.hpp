@@ -34,9 +34,28 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
 }
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __builtin_bit_cast(float, uint32_t(b) << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf(x) by Abramowitz & Stegun, Handbook of Mathematical Functions, formula
+// 7.1.26 (|error| <= 1.5e-7, below the BF16 rounding that follows every
+// activation): erf(x) = 1 - t (a1 + t (a2 + ...)) exp(-x^2), t = 1/(1 + p x),
+// x >= 0, odd extension.  g = exp(-x^2) is returned for the GELU derivative.
+__device__ __forceinline__ float erf_as(float x, float& g) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  g = __expf(-ax * ax);
+  const float e = 1.0f - poly * g;
+  return x < 0.0f ? -e : e;
+}
+
+// GELU with the error function (exact form 0.5 z (1 + erf(z / sqrt 2))) and its derivative.
+__device__ __forceinline__ float gelu(float z) {
+  float g;
+  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f, g));
+}
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+  float g;  // exp(-z^2 / 2)
+  const float e = erf_as(z * 0.70710678118654752f, g);
+  return 0.5f * (1.0f + e) + z * g * 0.39894228040143268f;
 }
 
 // One 16 x 16 output tile of A (M x K) * B (K x N) from BF16 values in LDS:

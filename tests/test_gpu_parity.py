@@ -199,23 +199,50 @@ def _neighbourhood_step(L, N, tau, nodes, g_of, shape):
     return rr.collide(L, N, tau, pulled)
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp64"])
-def test_full_size_d3q27_sampled_parity(lbrr, gpu, storage):
-    """256^3 D3Q27 order 4 (the benchmark launch): two steps, sampled nodes computed by the oracle alone."""
-    cfg = W.WORKLOADS["tgv3d_256_ma01"]
-    n, tau = cfg["n"], cfg["tau"]
-    shape = (n, n, n)
-    rho, u = W.tgv3d(n, cfg["u0"])
-    L = OL.lattice("D3Q27")
-    N = 4
-    print(f"full-size D3Q27 {storage} 256^3 two steps", flush=True)
-    sim = lbrr.Simulation("D3Q27", shape, tau, N, storage=storage)
+_field_cache = {}
+
+
+def full_size_fields(name):
+    """Input fields of the full-size workloads (cached: the 512^3 field takes tens of seconds)."""
+    if name not in _field_cache:
+        cfg = W.WORKLOADS[name]
+        if name.startswith("tgv3d"):
+            _field_cache[name] = W.tgv3d(cfg["n"], cfg["u0"])
+        elif name.startswith("solenoidal"):
+            _field_cache.clear()  # keep at most one large field
+            _field_cache[name] = W.random_solenoidal3d(cfg["n"], cfg["kmax"], cfg["urms"], 0)
+        else:
+            _field_cache[name] = W.shear_layer(cfg["n"], cfg["u0"], 0)
+    return _field_cache[name]
+
+
+FULL = [("tgv3d_256_ma01", "fp32"), ("tgv3d_256_ma01", "fp64"), ("tgv3d_256_ma01", "fp16"),
+        ("solenoidal_512_d3q27", "fp32"), ("solenoidal_512_d3q19", "fp32"), ("solenoidal_512_d3q19", "fp16"),
+        ("shear_2048_ma05", "fp32"), ("shear_2048_ma05", "fp16")]
+
+
+@pytest.mark.parametrize("name,storage", FULL)
+def test_full_size_sampled_parity(lbrr, gpu, name, storage):
+    """Workloads at their full size, in the launch configuration of the benchmark: two steps on the
+    GPU; rho and u at sampled nodes (random, corners, wrap edges) computed by the oracle alone from
+    the same input fields."""
+    cfg = W.WORKLOADS[name]
+    lat, n, tau, N = cfg["lattice"], cfg["n"], cfg["tau"], cfg["order"]
+    L = OL.lattice(lat)
+    shape = (n, n, n) if L.D == 3 else (1, n, n)
+    print(f"full-size {name} {lat} {storage} {shape} two steps", flush=True)
+    rho, u = full_size_fields(name)
+    sim = lbrr.Simulation(lat, shape, tau, N, storage=storage)
     sim.init_fields(rho, u)
     sim.step(2)
     r_gpu, u_gpu = (x.cpu().numpy() for x in sim.moments())
     sim.close()
     rng = np.random.default_rng(0)
-    pts = np.concatenate([rng.integers(0, n, size=(24, 3)), [[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0]]])
+    nz = shape[0]
+    pts = rng.integers(0, n, size=(24, 3))
+    pts[:, 0] %= nz
+    edges = [[0, 0, 0], [nz - 1, n - 1, n - 1], [0, n - 1, 0], [nz - 1, 0, n - 1]]
+    pts = np.concatenate([pts, edges])
 
     def g0(nodes):
         z, y, x = nodes.T
@@ -228,7 +255,7 @@ def test_full_size_d3q27_sampled_parity(lbrr, gpu, storage):
     g2 = _neighbourhood_step(L, N, tau, pts, g1, shape)
     r_ref, u_ref, _ = rr.moments(L, g2)
     idx = tuple(pts.T)
-    tol = 1e-12 if storage == "fp64" else 1e-5
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 5e-3}[storage]
     e_r = np.abs(r_gpu[idx] - r_ref).max()
     e_u = np.abs(u_gpu[(slice(None),) + idx] - u_ref).max() / np.abs(u_ref).max()
     print(f"  sampled err rho {e_r:.2e} u {e_u:.2e}", flush=True)
