@@ -18,6 +18,7 @@ namespace lbrr {
 namespace {
 
 using namespace mlp;
+static_assert(kMlpNPacked == kNPacked && kMlpNParam == kNParam && kMlpNNorm == kNNorm, "closure.hpp sizes");
 
 // ---------------------------------------------------------------------------
 // Coarse-graining of fine fields by F x F box averages (acoustic scaling:
@@ -139,50 +140,91 @@ __global__ void __launch_bounds__(256) k_features(const S* __restrict__ src, con
 }
 
 // ---------------------------------------------------------------------------
-// Forward pass of 64 samples per wave; every thread of the block calls it
-// (barriers inside).  feat: the lane's raw features; returns the lane's
-// de-normalised outputs.  LDS: weights (kNPacked BF16) and 1/std of the
-// features shared by the block, two 8 KiB regions per wave.
-__device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uint16_t* w, uint16_t* regA,
-                                             uint16_t* regB, const float* __restrict__ params,
-                                             const float* __restrict__ norm, const float* inv_std,
-                                             float (&out)[kOut]) {
-  const int lane = threadIdx.x & 63;
-  // normalised BF16 features, row = lane, 48 columns (zero padded)
-  for (int k = 0; k < kInP; ++k) {
-    const float v = (k < kIn) ? (feat[k] - norm[k]) * inv_std[k] : 0.0f;
-    regA[lane * kInP + k] = to_bf16(v);
+// Per-block constants of the inference kernels, staged in LDS: biases b1 (64),
+// b2 (64), b3 (3, padded to 4), then x_mean (36), 1/x_std (36), y_mean (3), y_std (3).
+constexpr int kCB1 = 0, kCB2 = kCB1 + kH, kCB3 = kCB2 + kH, kCMean = kCB3 + 4, kCInv = kCMean + kIn,
+              kCYMean = kCInv + kIn, kCYStd = kCYMean + kOut, kNConst = kCYStd + kOut;
+// Per-wave activation region: 64 rows (one per sample) of kLdH BF16 values.
+constexpr int kRegion = 64 * kLdH;
+
+__device__ __forceinline__ void load_constants(const float* __restrict__ params, const float* __restrict__ norm,
+                                               float* c) {
+  for (int k = threadIdx.x; k < kNConst; k += blockDim.x) {
+    float v;
+    if (k < kCB2) v = params[kOffB1 + k];
+    else if (k < kCB3) v = params[kOffB2 + k - kCB2];
+    else if (k < kCMean) v = (k - kCB3 < kOut) ? params[kOffB3 + k - kCB3] : 0.0f;
+    else if (k < kCInv) v = norm[k - kCMean];
+    else if (k < kCYMean) v = 1.0f / norm[kIn + k - kCInv];
+    else v = norm[2 * kIn + k - kCYMean];
+    c[k] = v;
+  }
+}
+
+// Forward pass of the 64 samples of a wave (sample s = lane s); every thread
+// of the block calls it (barriers inside).  The products are computed
+// transposed, features x samples (weights as the matrix-core A operand), so a
+// lane's result, four consecutive features of one sample, goes to the
+// sample's LDS row with one 8-byte write and is read back as the next layer's
+// operand with one 8-byte read.  feat: the lane's raw features; w: packed
+// weights in LDS; r0, r1: the wave's two activation regions; c: constants.
+__device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uint16_t* w, uint16_t* r0, uint16_t* r1,
+                                             const float* c, float (&out)[kOut]) {
+  const int lane = threadIdx.x & 63, q = lane >> 4;
+  // standardised BF16 features, row = sample (stride kLd1, inputs 36..47 zero)
+  bf16x4* xr = reinterpret_cast<bf16x4*>(r0 + lane * kLd1);
+#pragma unroll
+  for (int k4 = 0; k4 < kInP / 4; ++k4) {
+    bf16x4 v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * k4 + r;
+      v[r] = short(k < kIn ? to_bf16((feat[k] - c[kCMean + k]) * c[kCInv + k]) : uint16_t(0));
+    }
+    xr[k4] = v;
   }
   __syncthreads();
-  // layer 1: H1 = gelu(X W1^T + b1) -> regB [64][64]
+  // layer 1: H1 = gelu(W1 X + b1), 4 x 4 tiles (features j0, samples s0) -> r1
+#pragma unroll
   for (int t = 0; t < 16; ++t) {
-    const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
+    const int j0 = 16 * (t & 3), s0 = 16 * (t >> 2);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile_kc<kInP>(regA, kInP, w + kPW1, kInP, i0, j0, acc);
-    const int j = tile_col(j0);
-    for (int r = 0; r < 4; ++r) regB[tile_row(i0, r) * kH + j] = to_bf16(gelu(acc[r] + params[kOffB1 + j]));
+    acc = tile_kc<kInP>(w + kPW1, kLd1, r0, kLd1, j0, s0, acc);
+    const int j = j0 + 4 * q;
+    bf16x4 h;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = short(to_bf16(gelu(acc[r] + c[kCB1 + j + r])));
+    *reinterpret_cast<bf16x4*>(r1 + (s0 + (lane & 15)) * kLdH + j) = h;
   }
   __syncthreads();
-  // layer 2: H2 = gelu(H1 W2^T + b2) -> regA [64][64]
+  // layer 2: H2 = gelu(W2 H1 + b2) -> r0
+#pragma unroll
   for (int t = 0; t < 16; ++t) {
-    const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
+    const int j0 = 16 * (t & 3), s0 = 16 * (t >> 2);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile_kc<kH>(regB, kH, w + kPW2, kH, i0, j0, acc);
-    const int j = tile_col(j0);
-    for (int r = 0; r < 4; ++r) regA[tile_row(i0, r) * kH + j] = to_bf16(gelu(acc[r] + params[kOffB2 + j]));
+    acc = tile_kc<kH>(w + kPW2, kLdH, r1, kLdH, j0, s0, acc);
+    const int j = j0 + 4 * q;
+    bf16x4 h;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = short(to_bf16(gelu(acc[r] + c[kCB2 + j + r])));
+    *reinterpret_cast<bf16x4*>(r0 + (s0 + (lane & 15)) * kLdH + j) = h;
   }
   __syncthreads();
-  // layer 3: Y = H2 W3^T + b3 -> regB as FP32 [64][16]
-  float* ys = reinterpret_cast<float*>(regB);
+  // layer 3: Y = W3 H2 + b3 (rows 0..2 of one 16-row tile), FP32 -> r1 as [64][4]
+  float* ys = reinterpret_cast<float*>(r1);
+#pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int i0 = 16 * t;
+    const int s0 = 16 * t;
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile_kc<kH>(regA, kH, w + kPW3, kH, i0, 0, acc);
-    const int j = tile_col(0);
-    for (int r = 0; r < 4; ++r) ys[tile_row(i0, r) * kOutP + j] = acc[r] + (j < kOut ? params[kOffB3 + j] : 0.0f);
+    acc = tile_kc<kH>(w + kPW3, kLdH, r0, kLdH, 0, s0, acc);
+    if (q == 0) {
+#pragma unroll
+      for (int o = 0; o < kOut; ++o) ys[(s0 + lane) * 4 + o] = acc[o] + c[kCB3 + o];
+    }
   }
   __syncthreads();
-  for (int c = 0; c < kOut; ++c) out[c] = ys[lane * kOutP + c] * norm[2 * kIn + kOut + c] + norm[2 * kIn + c];
+#pragma unroll
+  for (int o = 0; o < kOut; ++o) out[o] = ys[lane * 4 + o] * c[kCYStd + o] + c[kCYMean + o];
   __syncthreads();
 }
 
@@ -194,20 +236,21 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(const float* __r
                                                                 const float* __restrict__ params,
                                                                 const float* __restrict__ norm, float* __restrict__ y) {
   __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
-  __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][64 * 64];
-  __shared__ float inv_std[kIn];
-  load_weights(packed, w);
-  if (threadIdx.x < kIn) inv_std[threadIdx.x] = 1.0f / norm[kIn + threadIdx.x];
+  __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][kRegion];
+  __shared__ __attribute__((aligned(16))) float cst[kNConst];
+  load_weights<64 * kInferWaves>(packed, w);
+  load_constants(params, norm, cst);
   const int wave = threadIdx.x >> 6;
   const int64_t s = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t sc = s < n ? s : n - 1;  // every lane takes part in the matrix-core tiles
   float feat[kIn];
+#pragma unroll
   for (int k = 0; k < kIn; ++k) feat[k] = x[sc * kIn + k];
   __syncthreads();
   float out[kOut];
-  forward_wave(feat, w, reg[wave][0], reg[wave][1], params, norm, inv_std, out);
+  forward_wave(feat, w, reg[wave][0], reg[wave][1], cst, out);
   if (s < n)
-    for (int c = 0; c < kOut; ++c) y[s * kOut + c] = out[c];
+    for (int o = 0; o < kOut; ++o) y[s * kOut + o] = out[o];
 }
 
 // ---------------------------------------------------------------------------
@@ -227,20 +270,20 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
                                                    const float* __restrict__ params, const float* __restrict__ norm,
                                                    float* __restrict__ gpart, float* __restrict__ lpart) {
   __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
-  __shared__ __attribute__((aligned(16))) uint16_t xs[kTS * kInP];
-  __shared__ __attribute__((aligned(16))) uint16_t h1s[kTS * kH];
-  __shared__ __attribute__((aligned(16))) uint16_t h2s[kTS * kH];
-  __shared__ __attribute__((aligned(16))) uint16_t dys[kTS * kOutP], dz2s[kTS * kH], dz1s[kTS * kH];
+  __shared__ __attribute__((aligned(16))) uint16_t xs[kTS * kLd1];
+  __shared__ __attribute__((aligned(16))) uint16_t h1s[kTS * kLdH];
+  __shared__ __attribute__((aligned(16))) uint16_t h2s[kTS * kLdH];
+  __shared__ __attribute__((aligned(16))) uint16_t dys[kTS * kOutP], dz2s[kTS * kLdH], dz1s[kTS * kLdH];
   __shared__ float z1[kTS * kH], z2[kTS * kH], ys[kTS * kOutP], ts[kTS * kOut], red[kTS * kOut];
   const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int s0 = blockIdx.x * kTS;
   float* g = gpart + int64_t(blockIdx.x) * kNParam;
-  load_weights(packed, w);
+  load_weights<256>(packed, w);
   for (int e = threadIdx.x; e < kTS * kInP; e += blockDim.x) {
     const int s = e / kInP, k = e % kInP, si = s0 + s;
     float v = 0.0f;
     if (k < kIn && si < batch) v = (x[clamp_row(idx[si], nrows) * kIn + k] - norm[k]) / norm[kIn + k];
-    xs[e] = to_bf16(v);
+    xs[s * kLd1 + k] = to_bf16(v);
   }
   for (int e = threadIdx.x; e < kTS * kOut; e += blockDim.x) {
     const int s = e / kOut, c = e % kOut, si = s0 + s;
@@ -252,33 +295,33 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   for (int t = wave; t < 8; t += nw) {  // layer 1: 2 x 4 tiles
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile_kc<kInP>(xs, kInP, w + kPW1, kInP, i0, j0, acc);
+    acc = tile_kc<kInP>(xs, kLd1, w + kPW1, kLd1, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) {
       const int i = tile_row(i0, r);
       const float zz = acc[r] + params[kOffB1 + j];
       z1[i * kH + j] = zz;
-      h1s[i * kH + j] = to_bf16(gelu(zz));
+      h1s[i * kLdH + j] = to_bf16(gelu(zz));
     }
   }
   __syncthreads();
   for (int t = wave; t < 8; t += nw) {  // layer 2
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile_kc<kH>(h1s, kH, w + kPW2, kH, i0, j0, acc);
+    acc = tile_kc<kH>(h1s, kLdH, w + kPW2, kLdH, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) {
       const int i = tile_row(i0, r);
       const float zz = acc[r] + params[kOffB2 + j];
       z2[i * kH + j] = zz;
-      h2s[i * kH + j] = to_bf16(gelu(zz));
+      h2s[i * kLdH + j] = to_bf16(gelu(zz));
     }
   }
   __syncthreads();
   for (int t = wave; t < 2; t += nw) {  // layer 3: 2 x 1 tiles
     const int i0 = 16 * t;
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile_kc<kH>(h2s, kH, w + kPW3, kH, i0, 0, acc);
+    acc = tile_kc<kH>(h2s, kLdH, w + kPW3, kLdH, i0, 0, acc);
     const int j = tile_col(0);
     for (int r = 0; r < 4; ++r) ys[tile_row(i0, r) * kOutP + j] = acc[r] + (j < kOut ? params[kOffB3 + j] : 0.0f);
   }
@@ -312,7 +355,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   for (int t = wave; t < 4; t += nw) {
     const int j0 = 16 * t;
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kTS>(dys, 1, kOutP, h2s, kH, 1, 0, j0, acc);
+    acc = tile<kTS>(dys, 1, kOutP, h2s, kLdH, 1, 0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) {
       const int o = tile_row(0, r);
@@ -323,13 +366,13 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   for (int t = wave; t < 8; t += nw) {
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kOutP>(dys, kOutP, 1, w + kPW3, kH, 1, i0, j0, acc);
+    acc = tile<kOutP>(dys, kOutP, 1, w + kPW3, kLdH, 1, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) {
       const int i = tile_row(i0, r);
       const float d = acc[r] * gelu_grad(z2[i * kH + j]);
       z2[i * kH + j] = d;
-      dz2s[i * kH + j] = to_bf16(d);
+      dz2s[i * kLdH + j] = to_bf16(d);
     }
   }
   __syncthreads();
@@ -341,20 +384,20 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   for (int t = wave; t < 16; t += nw) {  // dW2 = dZ2^T H1, 4 x 4 tiles, K = samples
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kTS>(dz2s, 1, kH, h1s, kH, 1, i0, j0, acc);
+    acc = tile<kTS>(dz2s, 1, kLdH, h1s, kLdH, 1, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) g[kOffW2 + tile_row(i0, r) * kH + j] = acc[r];
   }
   for (int t = wave; t < 8; t += nw) {  // dZ1 = (dZ2 W2) * gelu'(z1)
     const int i0 = 16 * (t >> 2), j0 = 16 * (t & 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kH>(dz2s, kH, 1, w + kPW2, kH, 1, i0, j0, acc);
+    acc = tile<kH>(dz2s, kLdH, 1, w + kPW2, kLdH, 1, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r) {
       const int i = tile_row(i0, r);
       const float d = acc[r] * gelu_grad(z1[i * kH + j]);
       z1[i * kH + j] = d;
-      dz1s[i * kH + j] = to_bf16(d);
+      dz1s[i * kLdH + j] = to_bf16(d);
     }
   }
   __syncthreads();
@@ -366,7 +409,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(const float* __restrict__ x, 
   for (int t = wave; t < 12; t += nw) {  // dW1 = dZ1^T X, 4 x 3 tiles, K = samples
     const int i0 = 16 * (t / 3), j0 = 16 * (t % 3);
     f32x4 acc = {0, 0, 0, 0};
-    acc = tile<kTS>(dz1s, 1, kH, xs, kInP, 1, i0, j0, acc);
+    acc = tile<kTS>(dz1s, 1, kLdH, xs, kLd1, 1, i0, j0, acc);
     const int j = tile_col(j0);
     for (int r = 0; r < 4; ++r)
       if (j < kIn) g[kOffW1 + tile_row(i0, r) * kIn + j] = acc[r];
@@ -437,19 +480,20 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, float* __re
   p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
-// FP32 parameters -> padded BF16 weight blocks.
+// FP32 parameters -> padded BF16 weight blocks (layout of the packed vector above).
 __global__ void __launch_bounds__(256) k_pack(const float* __restrict__ params, uint16_t* __restrict__ packed) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= kNPacked) return;
   float v = 0.0f;
   if (e < kPW2) {
-    const int o = e / kInP, k = e % kInP;
+    const int o = e / kLd1, k = e % kLd1;
     if (k < kIn) v = params[kOffW1 + o * kIn + k];
   } else if (e < kPW3) {
-    v = params[kOffW2 + (e - kPW2)];
+    const int o = (e - kPW2) / kLdH, k = (e - kPW2) % kLdH;
+    if (k < kH) v = params[kOffW2 + o * kH + k];
   } else {
-    const int o = (e - kPW3) / kH, k = (e - kPW3) % kH;
-    if (o < kOut) v = params[kOffW3 + o * kH + k];
+    const int o = (e - kPW3) / kLdH, k = (e - kPW3) % kLdH;
+    if (o < kOut && k < kH) v = params[kOffW3 + o * kH + k];
   }
   packed[e] = to_bf16(v);
 }
@@ -467,10 +511,10 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_step_closure(const S* __re
                                                                    const float* __restrict__ norm) {
   using R = typename Prec<S>::R;
   __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
-  __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][64 * 64];
-  __shared__ float inv_std[kIn];
-  load_weights(packed, w);
-  if (threadIdx.x < kIn) inv_std[threadIdx.x] = 1.0f / norm[kIn + threadIdx.x];
+  __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][kRegion];
+  __shared__ __attribute__((aligned(16))) float cst[kNConst];
+  load_weights<64 * kInferWaves>(packed, w);
+  load_constants(params, norm, cst);
   const int xr = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = xr < a.nx;
   const int x = active ? xr : xr % a.nx;
@@ -481,7 +525,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_step_closure(const S* __re
   features36<R>(f, m, a, x, y, feat);
   __syncthreads();
   float d[kOut];
-  forward_wave(feat, w, reg[threadIdx.x >> 6][0], reg[threadIdx.x >> 6][1], params, norm, inv_std, d);
+  forward_wave(feat, w, reg[threadIdx.x >> 6][0], reg[threadIdx.x >> 6][1], cst, d);
   const Moments<R> mo = raw_moments<D2Q9, R>(f);
   Hydro<R> h = hydro<D2Q9, R>(mo, R(a.rho0));
   h.axx += R(d[0]);

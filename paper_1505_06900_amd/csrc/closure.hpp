@@ -11,7 +11,7 @@ namespace lbrr {
 
 constexpr int kMlpNParam = 6723;  // W1 64x36, b1, W2 64x64, b2, W3 3x64, b3
 constexpr int kMlpNNorm = 78;     // x_mean 36, x_std 36, y_mean 3, y_std 3
-constexpr int kMlpNPacked = 8192; // BF16 weights, padded
+constexpr int kMlpNPacked = 8768; // BF16 weights, padded rows (layout in mlp.hpp)
 constexpr int kMlpIn = 36;
 
 hipError_t closure_step(int order, int storage, const void* src, void* dst, float* m, const StepArgs& a,

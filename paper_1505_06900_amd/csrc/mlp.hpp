@@ -5,8 +5,11 @@
 // Parameter vector (FP32, 6723 values): W1 (64 x 36, out x in), b1 (64),
 // W2 (64 x 64), b2 (64), W3 (3 x 64), b3 (3).  Normalisation vector (78):
 // x_mean (36), x_std (36), y_mean (3), y_std (3).
-// Packed BF16 weights (8192 values): W1 as 64 x 48 (in padded with zeros),
-// W2 as 64 x 64, W3 as 16 x 64 (outputs padded with zero rows).
+// Packed BF16 weights (8768 values, copied verbatim into LDS): W1 as 64 rows
+// of stride 52 (inputs 36..51 zero), W2 as 64 rows of stride 68, W3 as 16 rows
+// of stride 68 (outputs 3..15 zero; columns 64..67 of W2 and W3 zero).  The
+// row strides are 8 bytes modulo 128, so the 8-byte matrix-core operand reads
+// of 16 consecutive rows fall on distinct LDS bank pairs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,7 +24,9 @@ constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kH * kIn, kOffW2 = kOffB1 + kH, kOff
               kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kOut * kH, kNParam = kOffB3 + kOut;
 static_assert(kNParam == 6723, "parameter count");
 constexpr int kNNorm = 2 * kIn + 2 * kOut;
-constexpr int kPW1 = 0, kPW2 = kPW1 + kH * kInP, kPW3 = kPW2 + kH * kH, kNPacked = kPW3 + kOutP * kH;
+constexpr int kLd1 = 52, kLdH = 68;  // LDS row strides (BF16 elements) of 48- and 64-wide operands
+constexpr int kPW1 = 0, kPW2 = kPW1 + kH * kLd1, kPW3 = kPW2 + kH * kLdH, kNPacked = kPW3 + kOutP * kLdH;
+static_assert((kNPacked * 2) % 16 == 0 && (kPW2 * 2) % 16 == 0 && (kPW3 * 2) % 16 == 0, "16-byte packed blocks");
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -98,9 +103,25 @@ __device__ __forceinline__ f32x4 tile_kc(const uint16_t* A, int lda, const uint1
 __device__ __forceinline__ int tile_row(int i0, int r) { return i0 + 4 * ((threadIdx.x & 63) >> 4) + r; }
 __device__ __forceinline__ int tile_col(int j0) { return j0 + (threadIdx.x & 15); }
 
-// Load the packed BF16 weights (kNPacked values) into LDS with the whole block.
+// Load the packed BF16 weights into LDS with a block of NT threads, 16 bytes
+// per load, every load of a thread issued before its first LDS write.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+template <int NT>
 __device__ __forceinline__ void load_weights(const uint16_t* __restrict__ packed, uint16_t* lds) {
-  for (int k = threadIdx.x; k < kNPacked; k += blockDim.x) lds[k] = packed[k];
+  constexpr int kChunks = kNPacked * 2 / 16, kPer = (kChunks + NT - 1) / NT;
+  const u32x4* src = reinterpret_cast<const u32x4*>(packed);
+  u32x4* dst = reinterpret_cast<u32x4*>(lds);
+  u32x4 v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int c = int(threadIdx.x) + k * NT;
+    if (c < kChunks) v[k] = src[c];
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int c = int(threadIdx.x) + k * NT;
+    if (c < kChunks) dst[c] = v[k];
+  }
 }
 
 }  // namespace mlp
