@@ -27,6 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+STORAGE_NAMES = {"fp32": "FP32 population storage", "fp16": "FP16 population storage",
+                 "fp64": "FP64 population storage", "mom_fp32": "FP32 moment storage",
+                 "mom_fp64": "FP64 moment storage"}
 METRIC = "GLUPS + % HBM peak, D3Q27 RR-BGK 256³ FP32 vs FP16-store; L2 err vs FP64"
 WORKLOAD = "tgv3d_256_ma01"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_d3q27_o4_256.json")
@@ -36,8 +39,9 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Sources of the D3Q27 step kernel: the counters stay valid while these are unchanged.
-STEP_SOURCES = ("lattice.hpp", "collide.hpp", "ops.hpp", "kernels.hpp", "kernels_d3q27.hip")
+# Sources of the D3Q27 step kernels: the counters stay valid while these are unchanged.
+STEP_SOURCES = ("lattice.hpp", "collide.hpp", "ops.hpp", "kernels.hpp", "mkernels.hpp", "ops_impl.hpp",
+                "kernels_d3q27.hip")
 
 
 def kernel_source_hash():
@@ -234,14 +238,15 @@ def write_traffic(fetch_dir, write_dir, out_path):
     nodes = 256**3
     out = {"source_hash": kernel_source_hash(), "copy_calibration": {"fetch_factor": ff, "write_factor": fw},
            "workload": "D3Q27 order 4, 256^3, one step launch"}
-    tags = {"fp32": "float", "fp16": "DF16_", "fp64": "double"}
-    for st, tag in tags.items():
-        ks = [k for k in fetch if "k_step" in k and "D3Q27" in k and tag in k]
+    tags = {"fp32": ("k_step", "float"), "fp16": ("k_step", "DF16_"), "fp64": ("k_step", "double"),
+            "mom_fp32": ("k_mstep", "float"), "mom_fp64": ("k_mstep", "double")}
+    for st, (kern, tag) in tags.items():
+        ks = [k for k in fetch if kern in k and "D3Q27" in k and tag in k and "4" in k]
         if not ks:
             continue
         k = ks[0]
         b = (fetch[k] * ff + write[k] * fw) * 1024.0
-        alg = {"fp32": 216, "fp16": 108, "fp64": 432}[st] * nodes
+        alg = {"fp32": 216, "fp16": 108, "fp64": 432, "mom_fp32": 80, "mom_fp64": 160}[st] * nodes
         out[st] = {"kernel": k, "fetch_kib": fetch[k], "write_kib": write[k], "bytes_per_launch": round(b),
                    "algorithmic_bytes": alg, "ratio": round(b / alg, 5)}
     with open(out_path, "w") as fh:
@@ -287,7 +292,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure measurement")
-    ap.add_argument("--storages", default="fp32,fp16,fp64")
+    ap.add_argument("--storages", default="fp32,fp16,fp64,mom_fp32",
+                    help="state storages to time; the first one is the headline value")
     ap.add_argument("--probe", action="store_true", help="short launch sequence for rocprofv3 counter runs")
     ap.add_argument("--summarize-prof", nargs="+", metavar="DIR", help="summarise rocprofv3 CSV output and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -353,10 +359,11 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f32 (f16 storage)", "fp64": "f64"}[main_st],
+        "dtype": {"fp32": "f32", "fp16": "f32 (f16 storage)", "fp64": "f64", "mom_fp32": "f32 (moment storage)",
+                  "mom_fp64": "f64 (moment storage)"}[main_st],
         "data": "synthetic",
         "config": {"workload": "3D Taylor-Green vortex 256^3 periodic, D3Q27 order 4, Ma 0.1, Re 1600, "
-                               f"tau {cfg['tau']}, {main_st.upper()} population storage",
+                               f"tau {cfg['tau']}, {STORAGE_NAMES[main_st]}",
                    "lattice": "D3Q27", "order": cfg["order"], "nodes": nodes, "storage": main_st},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

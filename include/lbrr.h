@@ -31,12 +31,13 @@
  *    stay owned by the caller.
  *  - Population velocity order: i = (cx+1) + 3(cy+1) + 9(cz+1) for D2Q9
  *    (cz = 0) and D3Q27; D3Q19 keeps the D3Q27 order without the 8 corners.
- *  - The library owns two population buffers per handle (allocated with
- *    hipMalloc in lb_config / lb_init_fields, freed by lb_destroy).  They
- *    hold post-collision populations as deviations f_i - w_i rho0 in the
- *    storage type; rho and u of the stored state equal those of the
- *    pre-collision state at the same time because the collision conserves
- *    them (Sec. 2, mass and momentum conservation).
+ *  - The library owns two state buffers per handle (allocated with
+ *    hipMalloc in lb_init_fields / lb_set_populations, freed by lb_destroy).
+ *    With population storage they hold post-collision populations as
+ *    deviations f_i - w_i rho0 in the storage type; rho and u of the stored
+ *    state equal those of the pre-collision state at the same time because
+ *    the collision conserves them (Sec. 2, mass and momentum conservation).
+ *    With moment storage they hold the pre-collision moments (lb_config).
  *  - All device work is enqueued on the handle's stream (default: the null
  *    stream).  Entry points that return host data synchronise that stream.
  */
@@ -52,7 +53,13 @@ extern "C" {
 typedef struct lb_ctx* lb_handle;
 
 enum lb_lattice { LB_D2Q9 = 0, LB_D3Q19 = 1, LB_D3Q27 = 2 };
-enum lb_storage { LB_STORE_FP64 = 0, LB_STORE_FP32 = 1, LB_STORE_FP16 = 2 };
+enum lb_storage {
+  LB_STORE_FP64 = 0, /* populations f_i - w_i rho0, FP64 */
+  LB_STORE_FP32 = 1, /* populations f_i - w_i rho0, FP32 */
+  LB_STORE_FP16 = 2, /* populations f_i - w_i rho0, binary16 */
+  LB_STORE_MOM_FP64 = 3, /* moments rho - rho0, rho u, a1^(2) of each node, FP64 */
+  LB_STORE_MOM_FP32 = 4  /* moments rho - rho0, rho u, a1^(2) of each node, FP32 */
+};
 enum lb_dtype { LB_F64 = 0, LB_F32 = 1 };
 enum lb_status {
   LB_OK = 0,
@@ -74,11 +81,21 @@ enum lb_status {
  * allocated and no device work is launched.  Returns NULL on error. */
 lb_handle lb_create(int lattice, int nx, int ny, int nz, double tau, int order);
 
-/* Choose population storage (LB_STORE_*) and the reference density rho0 of
+/* Choose the state storage (LB_STORE_*) and the reference density rho0 of
  * the deviation form f_i - w_i rho0 (rho0 > 0, finite).  FP32 and FP16
  * storage collide in FP32, FP64 storage in FP64; FP16 values are rounded to
- * nearest-even on store, subnormals kept.  Must precede lb_init_fields /
- * lb_set_populations; calling it again discards the state. */
+ * nearest-even on store, subnormals kept.
+ * Moment storage (LB_STORE_MOM_*): after the collision of Eq. discr_bgk_reg
+ * the populations of a node are a function of its rho, u and a1^(2) only
+ * (a0 and the recursion of Sec. 3.1, reconstruction of Sec. 3.2), so the
+ * library stores each node's pre-collision (rho - rho0, rho u, a1^(2)) --
+ * 6 values in 2D, 10 in 3D -- and lb_step rebuilds each population of the
+ * source node before streaming it: the same update with 20 instead of 54
+ * stored values moved per D3Q27 node update.  Collision in FP64 or FP32 as
+ * the storage.  lb_set_populations and the learned closure are not available
+ * with moment storage (LB_ERR_UNSUPPORTED).
+ * Must precede lb_init_fields / lb_set_populations; calling it again discards
+ * the state. */
 int lb_config(lb_handle h, int storage, double rho0);
 
 /* Use hip_stream (a hipStream_t, may be NULL for the null stream) for all
@@ -108,9 +125,9 @@ int lb_set_check_interval(lb_handle h, long long k);
 
 /* Macroscopic fields of the current state: rho [nz][ny][nx], u [D][nz][ny][nx]
  * and, if pi1 != NULL, the off-equilibrium stress a1^(2) of the pre-collision
- * populations (Sec. 2, P^(1) = a1^(2)), recovered from the stored
- * post-collision state as its a1^(2) divided by (1 - 1/tau) (LB_ERR_UNSUPPORTED
- * when tau == 1).  Any of the outputs may be NULL.  Synchronises the stream. */
+ * populations (Sec. 2, P^(1) = a1^(2)), recovered from a stored
+ * post-collision population state as its a1^(2) divided by (1 - 1/tau)
+ * (LB_ERR_UNSUPPORTED when tau == 1; moment storage holds it directly).  Any of the outputs may be NULL.  Synchronises the stream. */
 int lb_moments(lb_handle h, void* rho, void* u, void* pi1, int dtype, int on_device);
 
 /* Global FP64 totals of the current state: out[0] = sum rho, out[1..3] =
@@ -128,16 +145,19 @@ int lb_enstrophy(lb_handle h, double* out);
 /* Copy the stored post-collision deviations f_i - w_i rho0 out of / into the
  * library, in the storage type, compact SoA [q][nz][ny][nx].  dst/src hold
  * q*nx*ny*nz elements.  lb_set_populations makes the handle ready to step
- * (step counter unchanged). */
+ * (step counter unchanged).  With moment storage lb_get_populations returns
+ * the post-collision deviations rebuilt from the stored moments (FP64 or FP32
+ * as the storage) and lb_set_populations returns LB_ERR_UNSUPPORTED. */
 int lb_get_populations(lb_handle h, void* dst, int on_device);
 int lb_set_populations(lb_handle h, const void* src, int on_device);
 
 /* Number of completed steps since lb_init_fields. */
 long long lb_step_count(lb_handle h);
 
-/* Bytes of population storage moved per lattice-node update by lb_step:
- * 2 * q * sizeof(storage element) (each population read once and written
- * once).  Returns 0 for a NULL handle. */
+/* Bytes of state storage moved per lattice-node update by lb_step: each
+ * stored value read once and written once, 2 * q * sizeof(element) for
+ * population storage, 2 * (1 + D + D(D+1)/2) * sizeof(element) for moment
+ * storage.  Returns 0 for a NULL handle. */
 double lb_bytes_per_update(lb_handle h);
 
 /* Release the handle and its device buffers (NULL-safe). */

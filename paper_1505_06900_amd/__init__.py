@@ -17,7 +17,7 @@ import ctypes
 from . import _lib
 from ._lib import (LB_D2Q9, LB_D3Q19, LB_D3Q27, LB_ERR_HIP, LB_ERR_INVALID_ARG, LB_ERR_OOM, LB_ERR_STATE,
                    LB_ERR_UNSTABLE, LB_ERR_UNSUPPORTED, LB_F32, LB_F64, LB_OK, LB_STORE_FP16, LB_STORE_FP32,
-                   LB_STORE_FP64, LBError)
+                   LB_STORE_FP64, LB_STORE_MOM_FP32, LB_STORE_MOM_FP64, LBError)
 
 
 def __getattr__(name):
@@ -40,7 +40,8 @@ def load():
 LATTICES = {"D2Q9": LB_D2Q9, "D3Q19": LB_D3Q19, "D3Q27": LB_D3Q27}
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
 DIM = {"D2Q9": 2, "D3Q19": 3, "D3Q27": 3}
-STORAGE = {"fp64": LB_STORE_FP64, "fp32": LB_STORE_FP32, "fp16": LB_STORE_FP16}
+STORAGE = {"fp64": LB_STORE_FP64, "fp32": LB_STORE_FP32, "fp16": LB_STORE_FP16,
+           "mom_fp64": LB_STORE_MOM_FP64, "mom_fp32": LB_STORE_MOM_FP32}
 
 check = _lib.check
 
@@ -56,7 +57,8 @@ class Simulation:
 
     lattice: "D2Q9" | "D3Q19" | "D3Q27"; shape (nz, ny, nx) with nz = 1 in 2D;
     tau: shifted relaxation time (nu = (tau - 1/2)/3); order: Hermite truncation;
-    storage: "fp64" | "fp32" | "fp16" (deviations f - w rho0).
+    storage: "fp64" | "fp32" | "fp16" (populations as deviations f - w rho0), or
+             "mom_fp64" | "mom_fp32" (per-node moments rho - rho0, rho u, a1^(2)).
     """
 
     def __init__(self, lattice, shape, tau, order, storage="fp32", rho0=1.0, stream=None):
@@ -87,7 +89,8 @@ class Simulation:
     @property
     def storage_dtype(self):
         torch = _torch()
-        return {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16}[self.storage]
+        return {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16, "mom_fp64": torch.float64,
+                "mom_fp32": torch.float32}[self.storage]
 
     # -- API -------------------------------------------------------------
     def init_fields(self, rho, u, pi1=None, dtype=None):

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "liblbrr.so")
 
 LB_D2Q9, LB_D3Q19, LB_D3Q27 = 0, 1, 2
 LB_STORE_FP64, LB_STORE_FP32, LB_STORE_FP16 = 0, 1, 2
+LB_STORE_MOM_FP64, LB_STORE_MOM_FP32 = 3, 4  # moment storage: rho - rho0, rho u, a1^(2) per node
 LB_F64, LB_F32 = 0, 1
 LB_OK = 0
 LB_ERR_INVALID_ARG = -1

@@ -40,7 +40,27 @@ int hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
-size_t elem_size(int storage) { return storage == LB_STORE_FP64 ? 8 : (storage == LB_STORE_FP32 ? 4 : 2); }
+size_t elem_size(int storage) {
+  switch (storage) {
+    case LB_STORE_FP64:
+    case LB_STORE_MOM_FP64: return 8;
+    case LB_STORE_FP32:
+    case LB_STORE_MOM_FP32: return 4;
+  }
+  return 2;
+}
+
+// z-planes per block of the moment-state step: each block rebuilds lz + 2
+// planes.  Fewer, shorter chunks measured faster on MI355X despite the extra
+// rebuilds (256^3 D3Q27 FP32: 36 GLUPS at 4, 25 at 8 and more); LBRR_MOM_LZ
+// overrides it.
+int moment_lz() {
+  if (const char* e = std::getenv("LBRR_MOM_LZ")) {
+    const int v = std::atoi(e);
+    if (v >= 1) return v;
+  }
+  return 4;
+}
 
 // Extra bytes after each population plane (layouts 0 and 2).  Planes whose
 // size is a large power of two would otherwise start at addresses that map to
@@ -88,6 +108,9 @@ struct lb_ctx {
   int64_t nodes() const { return int64_t(nx) * ny * nz; }
   int q() const { return ops->q; }
   int d() const { return ops->d; }
+  bool moment() const { return lbrr::is_moment_storage(storage); }
+  // stored values per node: q populations, or rho - rho0, j and a1^(2)
+  int nvalues() const { return moment() ? 1 + d() + d() * (d() + 1) / 2 : q(); }
   StepArgs args() const {
     StepArgs a;
     a.nx = nx;
@@ -98,6 +121,7 @@ struct lb_ctx {
     a.sz = sz;
     a.rho0 = rho0;
     a.omega1 = 1.0 - 1.0 / tau;
+    a.lz = moment_lz();
     return a;
   }
   void release() {
@@ -142,11 +166,22 @@ int layout_choice(int d, int64_t nx, int64_t ny, size_t es) {
   return (d == 3 && size_t(nx * ny) * es <= 262144) ? 2 : 1;
 }
 
+// Moment-state layout: the fields of a (y, z) row together ([z][y][c][x],
+// layout 1), so the patch of a step block reads one contiguous run per row.
+// LBRR_LAYOUT=0|1|2 overrides the choice.
+int moment_layout_choice() {
+  if (const char* e = std::getenv("LBRR_LAYOUT")) {
+    const int v = std::atoi(e);
+    if (v >= 0 && v <= 2) return v;
+  }
+  return 1;
+}
+
 int ensure_buffers(lb_ctx* h) {
   if (h->buf[0]) return LB_OK;
   const size_t es = elem_size(h->storage);
-  const int64_t nx = h->nx, ny = h->ny, nz = h->nz, q = h->q();
-  h->layout = layout_choice(h->d(), nx, ny, es);
+  const int64_t nx = h->nx, ny = h->ny, nz = h->nz, q = h->nvalues();
+  h->layout = h->moment() ? moment_layout_choice() : layout_choice(h->d(), nx, ny, es);
   size_t elems = 0;
   if (h->layout == 1) {  // rows of all populations together
     h->si = nx;
@@ -265,7 +300,7 @@ lb_handle lb_create(int lattice, int nx, int ny, int nz, double tau, int order) 
 
 int lb_config(lb_handle h, int storage, double rho0) {
   if (int r = check_handle(h)) return r;
-  if (storage < LB_STORE_FP64 || storage > LB_STORE_FP16) return fail(LB_ERR_INVALID_ARG, "bad storage %d", storage);
+  if (storage < LB_STORE_FP64 || storage > LB_STORE_MOM_FP32) return fail(LB_ERR_INVALID_ARG, "bad storage %d", storage);
   if (!std::isfinite(rho0) || !(rho0 > 0)) return fail(LB_ERR_INVALID_ARG, "rho0 must be finite and > 0");
   if (h->buf[0]) HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   h->release();
@@ -331,6 +366,7 @@ int lb_step(lb_handle h, long long n) {
   if (int r = check_handle(h)) return r;
   if (n < 0) return fail(LB_ERR_INVALID_ARG, "n must be >= 0");
   if (!h->ready) return fail(LB_ERR_STATE, "lb_step before lb_init_fields / lb_set_populations");
+  if (h->closure_on && h->moment()) return fail(LB_ERR_UNSUPPORTED, "the learned closure needs population storage");
   const StepArgs a = h->args();
   for (long long k = 0; k < n; ++k) {
     hipError_t e = h->closure_on
@@ -353,8 +389,9 @@ int lb_moments(lb_handle h, void* rho, void* u, void* pi1, int dtype, int on_dev
   if (!h->ready) return fail(LB_ERR_STATE, "no state: call lb_init_fields or lb_set_populations first");
   if (dtype != LB_F64 && dtype != LB_F32) return fail(LB_ERR_INVALID_ARG, "bad dtype %d", dtype);
   const double om = 1.0 - 1.0 / h->tau;
-  if (pi1 && om == 0.0) return fail(LB_ERR_UNSUPPORTED, "pi1 is not recoverable from the stored state when tau == 1");
-  const double inv_om = pi1 ? 1.0 / om : 0.0;
+  if (pi1 && om == 0.0 && !h->moment())
+    return fail(LB_ERR_UNSUPPORTED, "pi1 is not recoverable from the stored state when tau == 1");
+  const double inv_om = (pi1 && !h->moment()) ? 1.0 / om : 0.0;
   const size_t es = dtype == LB_F64 ? 8 : 4;
   const size_t nodes = size_t(h->nodes());
   const int d = h->d(), nc = d * (d + 1) / 2;
@@ -412,7 +449,8 @@ int lb_get_populations(lb_handle h, void* dst, int on_device) {
   const size_t bytes = size_t(h->nodes()) * h->q() * elem_size(h->storage);
   void* d = dst;
   if (!on_device) HIP_TRY(hipMalloc(&d, bytes), "hipMalloc staging");
-  hipError_t e = h->ops->repack(h->storage, h->buf[h->cur], d, true, h->args(), h->stream);
+  hipError_t e = h->moment() ? h->ops->mpopulations(h->order, h->storage, h->buf[h->cur], d, h->args(), h->stream)
+                             : h->ops->repack(h->storage, h->buf[h->cur], d, true, h->args(), h->stream);
   if (e == hipSuccess && !on_device) e = hipMemcpyAsync(dst, d, bytes, hipMemcpyDeviceToHost, h->stream);
   hipError_t s = hipStreamSynchronize(h->stream);
   if (!on_device) (void)hipFree(d);
@@ -424,6 +462,8 @@ int lb_get_populations(lb_handle h, void* dst, int on_device) {
 int lb_set_populations(lb_handle h, const void* src, int on_device) {
   if (int r = check_handle(h)) return r;
   if (!src) return fail(LB_ERR_INVALID_ARG, "src must not be NULL");
+  if (h->moment())
+    return fail(LB_ERR_UNSUPPORTED, "moment storage holds only states reachable by the collision; use lb_init_fields");
   if (int r = ensure_buffers(h)) return r;
   const size_t bytes = size_t(h->nodes()) * h->q() * elem_size(h->storage);
   const void* d = src;
@@ -450,7 +490,7 @@ long long lb_step_count(lb_handle h) { return h ? h->steps : -1; }
 
 double lb_bytes_per_update(lb_handle h) {
   if (!h) return 0.0;
-  return 2.0 * h->q() * double(elem_size(h->storage));
+  return 2.0 * h->nvalues() * double(elem_size(h->storage));
 }
 
 void lb_destroy(lb_handle h) {
@@ -502,6 +542,7 @@ int workspace(size_t bytes, void** out) {
 int lb_set_closure(lb_handle h, const float* params, const float* norm, int enable) {
   if (int r = check_handle(h)) return r;
   if (h->lattice != LB_D2Q9) return fail(LB_ERR_UNSUPPORTED, "the learned closure is implemented for D2Q9 only");
+  if (enable && h->moment()) return fail(LB_ERR_UNSUPPORTED, "the learned closure needs population storage");
   if (!enable) {
     h->closure_on = false;
     return LB_OK;
@@ -527,6 +568,7 @@ int lb_closure_features(lb_handle h, const double* a_target, double plain_weight
   if (int r = check_handle(h)) return r;
   if (h->lattice != LB_D2Q9) return fail(LB_ERR_UNSUPPORTED, "the learned closure is implemented for D2Q9 only");
   if (!features || !labels) return fail(LB_ERR_INVALID_ARG, "features and labels must not be NULL");
+  if (h->moment()) return fail(LB_ERR_UNSUPPORTED, "closure features need population storage");
   if (!h->ready) return fail(LB_ERR_STATE, "no state");
   void* m = nullptr;
   if (int r = workspace(sizeof(float) * 3 * size_t(h->nodes()), &m)) return r;

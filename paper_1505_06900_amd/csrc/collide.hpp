@@ -153,6 +153,18 @@ __device__ __forceinline__ Moments<R> raw_moments(const R* f) {
   }
 }
 
+// 1/rho for rho = rho0 + drho rounded: the exact rounding error of the sum
+// (two-sum) corrects the reciprocal to first order.  Rounding rho to the
+// working precision would otherwise bias u = j/rho by up to half an ulp of
+// rho0 at every step, an error that accumulates in time.
+template <class R>
+__device__ __forceinline__ R inv_density(R rho0, R drho, R rho) {
+  const R bb = rho - rho0;
+  const R err = (rho0 - (rho - bb)) + (drho - bb);
+  const R inv = R(1) / rho;
+  return inv - inv * inv * err;
+}
+
 // rho, u and a1^(2) = Pi - rho cs2 I - rho u u, written with deviations:
 // Pi_ab = P'_ab + rho0 cs2 delta_ab, so a1_ab = P'_ab - drho cs2 delta_ab - j_a u_b.
 template <class L, class R>
@@ -161,14 +173,7 @@ __device__ __forceinline__ Hydro<R> hydro(const Moments<R>& m, R rho0) {
   Hydro<R> h;
   h.drho = m.d0;
   h.rho = rho0 + m.d0;
-  // 1/rho from the rounded sum rho0 + drho and its exact rounding error
-  // (two-sum), corrected to first order: rounding rho to the storage
-  // precision would otherwise bias u = j/rho by up to half an ulp of rho0 at
-  // every step, an error that accumulates in time.
-  const R bb = h.rho - rho0;
-  const R err = (rho0 - (h.rho - bb)) + (m.d0 - bb);
-  R inv = R(1) / h.rho;
-  inv = inv - inv * inv * err;
+  const R inv = inv_density(rho0, m.d0, h.rho);
   h.jx = m.jx;
   h.jy = m.jy;
   h.ux = m.jx * inv;

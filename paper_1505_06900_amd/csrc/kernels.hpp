@@ -340,64 +340,4 @@ hipError_t init_by_order(int order, int dtype, const void* rho, const void* u, c
   return hipErrorInvalidValue;
 }
 
-template <class L>
-struct OpsImpl {
-  static hipError_t step(int order, int storage, const void* src, void* dst, const StepArgs& a, hipStream_t s) {
-    switch (storage) {
-      case 0: return step_by_order<L, double>(order, src, dst, a, s);
-      case 1: return step_by_order<L, float>(order, src, dst, a, s);
-      case 2: return step_by_order<L, _Float16>(order, src, dst, a, s);
-    }
-    return hipErrorInvalidValue;
-  }
-  static hipError_t init(int order, int storage, int dtype, const void* rho, const void* u, const void* pi1,
-                         void* dst, const StepArgs& a, hipStream_t s) {
-    switch (storage) {
-      case 0: return init_by_order<L, double>(order, dtype, rho, u, pi1, dst, a, s);
-      case 1: return init_by_order<L, float>(order, dtype, rho, u, pi1, dst, a, s);
-      case 2: return init_by_order<L, _Float16>(order, dtype, rho, u, pi1, dst, a, s);
-    }
-    return hipErrorInvalidValue;
-  }
-  static hipError_t moments(int storage, int dtype, const void* src, void* rho, void* u, void* pi1,
-                            const StepArgs& a, double inv_omega1, hipStream_t s) {
-    switch (storage) {
-      case 0: return launch_moments<L, double>(dtype, src, rho, u, pi1, a, inv_omega1, s);
-      case 1: return launch_moments<L, float>(dtype, src, rho, u, pi1, a, inv_omega1, s);
-      case 2: return launch_moments<L, _Float16>(dtype, src, rho, u, pi1, a, inv_omega1, s);
-    }
-    return hipErrorInvalidValue;
-  }
-  static hipError_t totals(int storage, const void* src, double* partials, int nblocks, double* out,
-                           const StepArgs& a, hipStream_t s) {
-    switch (storage) {
-      case 0: return launch_totals<L, double>(src, partials, nblocks, out, a, s);
-      case 1: return launch_totals<L, float>(src, partials, nblocks, out, a, s);
-      case 2: return launch_totals<L, _Float16>(src, partials, nblocks, out, a, s);
-    }
-    return hipErrorInvalidValue;
-  }
-  static hipError_t velocity(int storage, const void* src, double* u, const StepArgs& a, hipStream_t s) {
-    switch (storage) {
-      case 0: return launch_velocity<L, double>(src, u, a, s);
-      case 1: return launch_velocity<L, float>(src, u, a, s);
-      case 2: return launch_velocity<L, _Float16>(src, u, a, s);
-    }
-    return hipErrorInvalidValue;
-  }
-  static hipError_t repack(int storage, const void* src, void* dst, bool to_compact, const StepArgs& a,
-                           hipStream_t s) {
-    switch (storage) {
-      case 0: return launch_repack<L, double>(src, dst, to_compact, a, s);
-      case 1: return launch_repack<L, float>(src, dst, to_compact, a, s);
-      case 2: return launch_repack<L, _Float16>(src, dst, to_compact, a, s);
-    }
-    return hipErrorInvalidValue;
-  }
-  static const LatticeOps& table() {
-    static const LatticeOps t = {L::Q, L::D, L::NMAX, &step, &init, &moments, &totals, &velocity, &repack};
-    return t;
-  }
-};
-
 }  // namespace lbrr

@@ -1,5 +1,5 @@
 // Kernel instantiations for the D2Q9 lattice.
-#include "kernels.hpp"
+#include "ops_impl.hpp"
 
 namespace lbrr {
 const LatticeOps& ops_d2q9() { return OpsImpl<D2Q9>::table(); }

@@ -1,5 +1,5 @@
 // Kernel instantiations for the D3Q19 lattice.
-#include "kernels.hpp"
+#include "ops_impl.hpp"
 
 namespace lbrr {
 const LatticeOps& ops_d3q19() { return OpsImpl<D3Q19>::table(); }

@@ -1,5 +1,5 @@
 // Kernel instantiations for the D3Q27 lattice.
-#include "kernels.hpp"
+#include "ops_impl.hpp"
 
 namespace lbrr {
 const LatticeOps& ops_d3q27() { return OpsImpl<D3Q27>::table(); }

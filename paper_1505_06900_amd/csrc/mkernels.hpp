@@ -1,0 +1,444 @@
+// Moment-state form of the regularised update.
+//
+// After the collision of Eq. discr_bgk_reg every population of a node is a
+// function of that node's rho, u and a1^(2) alone: f0 from a0_k = rho u^k and
+// f1 from a1^(2) through the recursion of Sec. 3.1 (Eq. rel_a1), both
+// reconstructed as in Sec. 3.2.  The state of a lattice node can therefore be
+// stored as its pre-collision moments
+//     m = (rho - rho0, j = rho u, a1^(2))       10 values in 3D, 6 in 2D,
+// instead of q populations, and one step of the scheme becomes: rebuild the
+// post-collision populations of every node from m, stream them (pull), and
+// take the moments of the populations that arrive.  This is the same update
+// in exact arithmetic, with 2 x 10 instead of 2 x 27 stored values moved per
+// D3Q27 node update.
+//
+// Storage: field c of node (x, y, z) at element c*si + z*sz + y*sy + x.
+// 3D fields: drho, jx, jy, jz, axx, ayy, azz, axy, axz, ayz; 2D: drho, jx,
+// jy, axx, ayy, axy.  FP64 or FP32; the collision runs in the same precision.
+//
+// Step kernel: a block rebuilds the populations of a kMX x TY patch of nodes
+// of one z-plane, exchanges them through LDS, and the inner (kMX-2) x (TY-2)
+// nodes pull theirs.  In 3D the block marches along z through a chunk of
+// planes: the populations rebuilt on plane p with c_z = -1, 0, +1 arrive on
+// planes p-1, p, p+1, so each inner thread keeps running moment sums for
+// three target planes, and plane p-1 is complete once plane p has been
+// rebuilt.  A chunk of lz target planes rebuilds lz + 2 planes; a patch
+// rebuilds its one-node halo ring as well.  The halo and chunk overlaps are
+// the price of the 2.7x smaller state: the kernel is bound by the rebuild
+// arithmetic, not by HBM.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace lbrr {
+
+template <class L>
+constexpr int kNM = (L::D == 3) ? 10 : 6;
+
+constexpr int kMX = 32;  // patch of rebuilt nodes per block: kMX x TY
+
+// Hydrodynamic state of a node from its stored moments m.
+template <class L, class R>
+__device__ __forceinline__ Hydro<R> state_hydro(const R (&m)[kNM<L>], R rho0) {
+  Hydro<R> h;
+  h.drho = m[0];
+  h.rho = rho0 + m[0];
+  const R inv = inv_density(rho0, m[0], h.rho);
+  h.jx = m[1];
+  h.jy = m[2];
+  h.ux = m[1] * inv;
+  h.uy = m[2] * inv;
+  if constexpr (L::D == 3) {
+    h.jz = m[3];
+    h.uz = m[3] * inv;
+    h.axx = m[4];
+    h.ayy = m[5];
+    h.azz = m[6];
+    h.axy = m[7];
+    h.axz = m[8];
+    h.ayz = m[9];
+  } else {
+    h.jz = h.uz = R(0);
+    h.axx = m[3];
+    h.ayy = m[4];
+    h.axy = m[5];
+    h.azz = h.axz = h.ayz = R(0);
+  }
+  return h;
+}
+
+// Stored moments of a node from the moment sums of its arrived populations.
+template <class L, class R>
+__device__ __forceinline__ void finalize_state(const Moments<R>& s, R rho0, R (&m)[kNM<L>]) {
+  const Hydro<R> h = hydro<L, R>(s, rho0);
+  m[0] = s.d0;
+  m[1] = s.jx;
+  m[2] = s.jy;
+  if constexpr (L::D == 3) {
+    m[3] = s.jz;
+    m[4] = h.axx;
+    m[5] = h.ayy;
+    m[6] = h.azz;
+    m[7] = h.axy;
+    m[8] = h.axz;
+    m[9] = h.ayz;
+  } else {
+    m[3] = h.axx;
+    m[4] = h.ayy;
+    m[5] = h.axy;
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void clear(Moments<R>& s) {
+  s.d0 = s.jx = s.jy = s.jz = s.pxx = s.pyy = s.pzz = s.pxy = s.pxz = s.pyz = R(0);
+}
+
+// Does the lattice carry velocity (cx, cy, cz)?
+template <class L>
+constexpr bool has_velocity(int cx, int cy, int cz) {
+  if (L::D == 2 && cz != 0) return false;
+  if (!L::kProduct && cx != 0 && cy != 0 && cz != 0) return false;
+  return true;
+}
+
+// Lattice index of velocity (cx, cy, cz) (must exist).
+template <class L>
+constexpr int velocity_index(int cx, int cy, int cz) {
+  for (int i = 0; i < L::Q; ++i)
+    if (L::cx(i) == cx && L::cy(i) == cy && L::cz(i) == cz) return i;
+  return -1;
+}
+
+// Add the populations of the layer c_z = CZ that arrive at inner node (tx, ty)
+// to its moment sums s: population (cx, cy, CZ) comes from patch node
+// (tx - cx, ty - cy).  Sums along x, then y, then the c_z factors.
+template <class L, int CZ, int TY, class R>
+__device__ __forceinline__ void add_layer(Moments<R>& s, const R (*pop)[TY][kMX], int tx, int ty) {
+  R r0[3], r1[3], r2[3];  // per row cy: sum of v, cx v, cx^2 v
+  sfor<0, 3>([&](auto Y) {
+    constexpr int cy = int(Y) - 1;
+    R v[3];
+    sfor<0, 3>([&](auto X) {
+      constexpr int cx = int(X) - 1;
+      if constexpr (has_velocity<L>(cx, cy, CZ)) v[X] = pop[velocity_index<L>(cx, cy, CZ)][ty - cy][tx - cx];
+      else v[X] = R(0);
+    });
+    constexpr bool side = has_velocity<L>(-1, cy, CZ);  // the +-1 entries come in pairs
+    if constexpr (side) {
+      const R e = v[2] + v[0];
+      r0[Y] = e + v[1];
+      r1[Y] = v[2] - v[0];
+      r2[Y] = e;
+    } else {
+      r0[Y] = v[1];
+      r1[Y] = R(0);
+      r2[Y] = R(0);
+    }
+  });
+  const R e0 = r0[2] + r0[0];
+  const R s00 = e0 + r0[1], s01 = r0[2] - r0[0], s02 = e0;
+  const R s10 = (r1[2] + r1[0]) + r1[1], s11 = r1[2] - r1[0];
+  const R s20 = (r2[2] + r2[0]) + r2[1];
+  s.d0 = s.d0 + s00;
+  s.jx = s.jx + s10;
+  s.jy = s.jy + s01;
+  s.pxx = s.pxx + s20;
+  s.pyy = s.pyy + s02;
+  s.pxy = s.pxy + s11;
+  if constexpr (CZ != 0) {
+    s.pzz = s.pzz + s00;
+    if constexpr (CZ > 0) {
+      s.jz = s.jz + s00;
+      s.pxz = s.pxz + s10;
+      s.pyz = s.pyz + s01;
+    } else {
+      s.jz = s.jz - s00;
+      s.pxz = s.pxz - s10;
+      s.pyz = s.pyz - s01;
+    }
+  }
+}
+
+// Block barrier for the LDS exchange: waits for the LDS accesses of every
+// wave but leaves global loads and stores in flight (threads of a block share
+// nothing through global memory here), so a prefetch survives the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// One step of the moment-state update (see the file comment).
+template <class L, int N, class S, int TY>
+__global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
+  using R = S;
+  constexpr int NM = kNM<L>;
+  __shared__ R pop[L::Q][TY][kMX];
+  const int tx = threadIdx.x % kMX, ty = threadIdx.x / kMX;
+  const int x0 = blockIdx.x * (kMX - 2), y0 = blockIdx.y * (TY - 2), bz = blockIdx.z;
+  // the patch node this thread rebuilds, and the node it updates if inner
+  const int px = wrap(x0 - 1 + tx, a.nx), py = wrap(y0 - 1 + ty, a.ny);
+  const bool inner = tx >= 1 && tx <= kMX - 2 && ty >= 1 && ty <= TY - 2 && x0 + tx - 1 < a.nx && y0 + ty - 1 < a.ny;
+  const int64_t col_in = int64_t(py) * a.sy + px;
+  const int64_t col_out = int64_t(y0 + ty - 1) * a.sy + (x0 + tx - 1);
+  const R rho0 = R(a.rho0), om = R(a.omega1);
+
+  auto load = [&](int z, R (&m)[NM]) {
+    const S* s = src + int64_t(z) * a.sz + col_in;
+    sfor<0, NM>([&](auto C) { m[C] = s[int64_t(C) * a.si]; });
+  };
+  auto rebuild = [&](const R (&m)[NM]) {
+    const Hydro<R> h = state_hydro<L, R>(m, rho0);
+    R C[3][3][3];
+    coefficients<L, N, R>(h, om, C);
+    R f[L::Q];
+    reconstruct<L, N, R>(C, f);
+    sfor<0, L::Q>([&](auto I) { pop[I][ty][tx] = f[I]; });
+  };
+  auto put = [&](int z, const R (&m)[NM]) {
+    S* d = dst + int64_t(z) * a.sz + col_out;
+    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], d + int64_t(C) * a.si); });
+  };
+
+  if constexpr (L::D == 2) {
+    R m[NM];
+    load(0, m);
+    rebuild(m);
+    lds_barrier();
+    if (inner) {
+      Moments<R> acc;
+      clear(acc);
+      add_layer<L, 0, TY, R>(acc, pop, tx, ty);
+      R m2[NM];
+      finalize_state<L, R>(acc, rho0, m2);
+      put(0, m2);
+    }
+  } else {
+    // The moments of a completed target plane are kept in registers and
+    // stored at the start of the next iteration, next to the prefetch of the
+    // plane after: both then have a whole rebuild to complete before the
+    // wait at the end of the iteration.
+    const int z0 = bz * a.lz;
+    const int z1 = (z0 + a.lz < a.nz) ? z0 + a.lz : a.nz;
+    Moments<R> prev, cur, next;  // sums of target planes p-1, p, p+1
+    clear(prev);
+    clear(cur);
+    clear(next);
+    R mn[NM];  // moments of the plane rebuilt next, loaded one iteration ahead
+    load(wrap(z0 - 1, a.nz), mn);
+    R out[NM];  // moments of target plane pz - 2, stored during iteration pz
+    for (int pz = z0 - 1; pz <= z1; ++pz) {
+      R m[NM];
+      sfor<0, NM>([&](auto C) { m[C] = mn[C]; });
+      if (pz < z1) load(wrap(pz + 1, a.nz), mn);
+      if (inner && pz >= z0 + 2) put(pz - 2, out);
+      rebuild(m);
+      lds_barrier();
+      if (inner) {
+        add_layer<L, -1, TY, R>(prev, pop, tx, ty);
+        add_layer<L, 0, TY, R>(cur, pop, tx, ty);
+        add_layer<L, 1, TY, R>(next, pop, tx, ty);
+        if (pz >= z0 + 1) finalize_state<L, R>(prev, rho0, out);  // target plane pz - 1 is complete
+        prev = cur;
+        cur = next;
+        clear(next);
+      }
+      lds_barrier();
+    }
+    if (inner) put(z1 - 1, out);
+  }
+}
+
+// Moment state at t = 0 from (rho, u[, pi1]): the pre-collision moments of
+// f0(rho, u) + f1(u, pi1), i.e. rho - rho0, rho u and pi1 (Sec. 3.2).
+template <class L, class S, class T>
+__global__ void __launch_bounds__(256) k_minit(const T* __restrict__ rho, const T* __restrict__ u,
+                                               const T* __restrict__ pi1, S* __restrict__ dst, StepArgs a) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = node_offset(a, uint32_t(n));
+  const double r = double(rho[n]);
+  S m[kNM<L>];
+  m[0] = S(r - a.rho0);
+  m[1] = S(r * double(u[n]));
+  m[2] = S(r * double(u[nodes + n]));
+  if constexpr (L::D == 3) {
+    m[3] = S(r * double(u[2 * nodes + n]));
+    // pi1 order xx, xy, xz, yy, yz, zz -> state order axx, ayy, azz, axy, axz, ayz
+    const int perm[6] = {0, 3, 5, 1, 2, 4};
+    for (int c = 0; c < 6; ++c) m[4 + c] = pi1 ? S(pi1[perm[c] * nodes + n]) : S(0);
+  } else {
+    const int perm[3] = {0, 2, 1};  // xx, xy, yy -> axx, ayy, axy
+    for (int c = 0; c < 3; ++c) m[3 + c] = pi1 ? S(pi1[perm[c] * nodes + n]) : S(0);
+  }
+  sfor<0, kNM<L>>([&](auto C) { dst[int64_t(C) * a.si + off] = m[C]; });
+}
+
+// rho, u, pi1 (= the stored pre-collision a1^(2)) of the moment state.
+template <class L, class S, class T>
+__global__ void __launch_bounds__(256) k_mmoments(const S* __restrict__ src, T* __restrict__ rho, T* __restrict__ u,
+                                                  T* __restrict__ pi1, StepArgs a) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = node_offset(a, uint32_t(n));
+  double m[kNM<L>];
+  sfor<0, kNM<L>>([&](auto C) { m[C] = double(src[int64_t(C) * a.si + off]); });
+  const double r = a.rho0 + m[0];
+  if (rho) rho[n] = T(r);
+  if (u) {
+    u[n] = T(m[1] / r);
+    u[nodes + n] = T(m[2] / r);
+    if constexpr (L::D == 3) u[2 * nodes + n] = T(m[3] / r);
+  }
+  if (pi1) {
+    if constexpr (L::D == 3) {
+      const int from[6] = {4, 7, 8, 5, 9, 6};  // xx, xy, xz, yy, yz, zz
+      for (int c = 0; c < 6; ++c) pi1[c * nodes + n] = T(m[from[c]]);
+    } else {
+      const int from[3] = {3, 5, 4};  // xx, xy, yy
+      for (int c = 0; c < 3; ++c) pi1[c * nodes + n] = T(m[from[c]]);
+    }
+  }
+}
+
+// Per-block partial totals {rho, j_x, j_y, j_z, |j|^2 / (2 rho)} of the moment state.
+template <class L, class S>
+__global__ void __launch_bounds__(kReduceBlock) k_mtotals(const S* __restrict__ src, double* __restrict__ partials,
+                                                          StepArgs a, int64_t per_block) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t begin = int64_t(blockIdx.x) * per_block;
+  const int64_t end = begin + per_block < nodes ? begin + per_block : nodes;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t n = begin + threadIdx.x; n < end; n += kReduceBlock) {
+    const int64_t off = node_offset(a, uint32_t(n));
+    const double r = a.rho0 + double(src[off]);
+    const double jx = double(src[a.si + off]), jy = double(src[2 * a.si + off]);
+    const double jz = (L::D == 3) ? double(src[3 * a.si + off]) : 0.0;
+    acc[0] += r;
+    acc[1] += jx;
+    acc[2] += jy;
+    acc[3] += jz;
+    acc[4] += 0.5 * (jx * jx + jy * jy + jz * jz) / r;
+  }
+  block_sum_store<5>(acc, partials);
+}
+
+// Velocity field (FP64) of the moment state.
+template <class L, class S>
+__global__ void __launch_bounds__(256) k_mvelocity(const S* __restrict__ src, double* __restrict__ u, StepArgs a) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = node_offset(a, uint32_t(n));
+  const double inv = 1.0 / (a.rho0 + double(src[off]));
+  u[n] = double(src[a.si + off]) * inv;
+  u[nodes + n] = double(src[2 * a.si + off]) * inv;
+  if constexpr (L::D == 3) u[2 * nodes + n] = double(src[3 * a.si + off]) * inv;
+}
+
+// Post-collision deviations of the moment state (what the population form
+// stores), compact SoA [q][node] in the state's precision.
+template <class L, int N, class S>
+__global__ void __launch_bounds__(256) k_mpopulations(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  const int64_t off = node_offset(a, uint32_t(n));
+  S m[kNM<L>];
+  sfor<0, kNM<L>>([&](auto C) { m[C] = src[int64_t(C) * a.si + off]; });
+  const Hydro<S> h = state_hydro<L, S>(m, S(a.rho0));
+  S C[3][3][3];
+  coefficients<L, N, S>(h, S(a.omega1), C);
+  S f[L::Q];
+  reconstruct<L, N, S>(C, f);
+  sfor<0, L::Q>([&](auto I) { dst[int64_t(I) * nodes + n] = f[I]; });
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.  a.lz = z-planes per block of the 3D step (each chunk rebuilds
+// lz + 2 planes); the host picks it.
+// Patch rows: 16 for FP32 (a 55 KiB exchange), 8 for FP64 (the same bytes).
+// Measured on the 256^3 D3Q27 step (FP32, fields of a row together): 8, 16
+// and 32 rows within 6%; 4 z-planes per chunk best (36 GLUPS), 8 and more
+// 30% slower; handing XCDs blocks of neighbouring tiles lowered the L2-miss
+// traffic by half but not the time.
+template <class L, int N, class S>
+hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream_t s) {
+  constexpr int TY = sizeof(S) == 4 ? 16 : 8;
+  if (L::D == 3 && a.lz < 1) return hipErrorInvalidValue;
+  dim3 grid(unsigned((a.nx + kMX - 3) / (kMX - 2)), unsigned((a.ny + TY - 3) / (TY - 2)),
+            unsigned(L::D == 3 ? (a.nz + a.lz - 1) / a.lz : 1));
+  if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_mstep<L, N, S, TY>), grid, dim3(kMX * TY), 0, s, static_cast<const S*>(src),
+                     static_cast<S*>(dst), a);
+  return hipGetLastError();
+}
+
+template <class L, int N, class S>
+hipError_t launch_mpopulations(const void* src, void* dst, const StepArgs& a, hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  hipLaunchKernelGGL((k_mpopulations<L, N, S>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const S*>(src), static_cast<S*>(dst), a);
+  return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_minit(int dtype, const void* rho, const void* u, const void* pi1, void* dst, const StepArgs& a,
+                        hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  dim3 grid(unsigned((nodes + 255) / 256));
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_minit<L, S, double>), grid, dim3(256), 0, s, static_cast<const double*>(rho),
+                       static_cast<const double*>(u), static_cast<const double*>(pi1), static_cast<S*>(dst), a);
+  else
+    hipLaunchKernelGGL((k_minit<L, S, float>), grid, dim3(256), 0, s, static_cast<const float*>(rho),
+                       static_cast<const float*>(u), static_cast<const float*>(pi1), static_cast<S*>(dst), a);
+  return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_mmoments(int dtype, const void* src, void* rho, void* u, void* pi1, const StepArgs& a,
+                           hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  dim3 grid(unsigned((nodes + 255) / 256));
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_mmoments<L, S, double>), grid, dim3(256), 0, s, static_cast<const S*>(src),
+                       static_cast<double*>(rho), static_cast<double*>(u), static_cast<double*>(pi1), a);
+  else
+    hipLaunchKernelGGL((k_mmoments<L, S, float>), grid, dim3(256), 0, s, static_cast<const S*>(src),
+                       static_cast<float*>(rho), static_cast<float*>(u), static_cast<float*>(pi1), a);
+  return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_mtotals(const void* src, double* partials, int nblocks, double* out, const StepArgs& a,
+                          hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  const int64_t per_block = (nodes + nblocks - 1) / nblocks;
+  hipLaunchKernelGGL((k_mtotals<L, S>), dim3(nblocks), dim3(kReduceBlock), 0, s, static_cast<const S*>(src),
+                     partials, a, per_block);
+  hipLaunchKernelGGL((k_final<5>), dim3(1), dim3(kReduceBlock), 0, s, partials, nblocks, out);
+  return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_mvelocity(const void* src, double* u, const StepArgs& a, hipStream_t s) {
+  const int64_t nodes = int64_t(a.nx) * a.ny * a.nz;
+  hipLaunchKernelGGL((k_mvelocity<L, S>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s,
+                     static_cast<const S*>(src), u, a);
+  return hipGetLastError();
+}
+
+}  // namespace lbrr

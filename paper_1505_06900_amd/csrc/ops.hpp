@@ -10,7 +10,7 @@ namespace lbrr {
 
 constexpr int kReduceBlock = 256;
 
-// Launch parameters shared by the kernels.  Population i of node (x, y, z)
+// Launch parameters shared by the kernels.  Population (or moment field) i of node (x, y, z)
 // lives at element i*si + z*sz + y*sy + x of a buffer; the host picks the
 // strides (layout) and checks that every index stays inside the allocation.
 struct StepArgs {
@@ -18,6 +18,7 @@ struct StepArgs {
   int64_t si, sy, sz;  // element strides of population, row and plane
   double rho0;         // reference density of the deviation storage
   double omega1;       // 1 - 1/tau
+  int lz;              // z-planes per block of the moment-state step (3D)
 };
 
 struct LatticeOps {
@@ -32,7 +33,13 @@ struct LatticeOps {
   hipError_t (*velocity)(int storage, const void* src, double* u, const StepArgs& a, hipStream_t s);
   // copy between the internal layout and compact SoA [q][nz][ny][nx] (to_compact: internal -> compact)
   hipError_t (*repack)(int storage, const void* src, void* dst, bool to_compact, const StepArgs& a, hipStream_t s);
+  // moment storage: post-collision deviations of the state, compact SoA [q][nz][ny][nx]
+  hipError_t (*mpopulations)(int order, int storage, const void* src, void* dst, const StepArgs& a, hipStream_t s);
 };
+
+// Storage kinds (values of lb_storage): populations 0 FP64, 1 FP32, 2 FP16;
+// moments 3 FP64, 4 FP32.
+constexpr bool is_moment_storage(int storage) { return storage == 3 || storage == 4; }
 
 const LatticeOps& ops_d2q9();
 const LatticeOps& ops_d3q19();

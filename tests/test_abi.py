@@ -59,3 +59,12 @@ def test_null_handle_calls_fail_cleanly(lbrr):
     assert lbrr.lb_bytes_per_update(None) == 0.0
     lbrr.lb_destroy(None)  # NULL-safe
     assert lbrr.lb_probe_copy(None, None, 16, None) == lbrr.LB_ERR_INVALID_ARG
+
+
+def test_header_enums_match_the_binding(lbrr):
+    """Every LB_* enumerator of the header has the value the Python binding uses."""
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "lbrr.h")).read(), flags=re.S)
+    vals = dict((k, int(v)) for k, v in re.findall(r"\b(LB_[A-Z0-9_]+)\s*=\s*(-?\d+)", text))
+    assert {"LB_STORE_MOM_FP64", "LB_STORE_MOM_FP32", "LB_ERR_UNSUPPORTED"} <= set(vals)
+    for k, v in vals.items():
+        assert getattr(lbrr, k) == v, k

@@ -217,8 +217,10 @@ def full_size_fields(name):
 
 
 FULL = [("tgv3d_256_ma01", "fp32"), ("tgv3d_256_ma01", "fp64"), ("tgv3d_256_ma01", "fp16"),
+        ("tgv3d_256_ma01", "mom_fp32"), ("tgv3d_256_ma01", "mom_fp64"),
         ("solenoidal_512_d3q27", "fp32"), ("solenoidal_512_d3q19", "fp32"), ("solenoidal_512_d3q19", "fp16"),
-        ("shear_2048_ma05", "fp32"), ("shear_2048_ma05", "fp16")]
+        ("solenoidal_512_d3q27", "mom_fp32"), ("solenoidal_512_d3q19", "mom_fp32"),
+        ("shear_2048_ma05", "fp32"), ("shear_2048_ma05", "fp16"), ("shear_2048_ma05", "mom_fp32")]
 
 
 @pytest.mark.parametrize("name,storage", FULL)
@@ -255,7 +257,7 @@ def test_full_size_sampled_parity(lbrr, gpu, name, storage):
     g2 = _neighbourhood_step(L, N, tau, pts, g1, shape)
     r_ref, u_ref, _ = rr.moments(L, g2)
     idx = tuple(pts.T)
-    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 5e-3}[storage]
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 5e-3, "mom_fp64": 1e-12, "mom_fp32": 1e-5}[storage]
     e_r = np.abs(r_gpu[idx] - r_ref).max()
     e_u = np.abs(u_gpu[(slice(None),) + idx] - u_ref).max() / np.abs(u_ref).max()
     print(f"  sampled err rho {e_r:.2e} u {e_u:.2e}", flush=True)
