@@ -103,7 +103,6 @@ struct lb_ctx {
   float* cl_params = nullptr;   // kMlpNParam
   float* cl_norm = nullptr;     // kMlpNNorm
   uint16_t* cl_packed = nullptr;
-  float* cl_m = nullptr;        // 3 * nodes: rho - rho0, u_x, u_y of the stored state
 
   int64_t nodes() const { return int64_t(nx) * ny * nz; }
   int q() const { return ops->q; }
@@ -138,13 +137,11 @@ struct lb_ctx {
     ready = false;
   }
   void release_closure() {
-    for (void* p : {static_cast<void*>(cl_params), static_cast<void*>(cl_norm), static_cast<void*>(cl_packed),
-                    static_cast<void*>(cl_m)})
+    for (void* p : {static_cast<void*>(cl_params), static_cast<void*>(cl_norm), static_cast<void*>(cl_packed)})
       if (p) (void)hipFree(p);
     cl_params = nullptr;
     cl_norm = nullptr;
     cl_packed = nullptr;
-    cl_m = nullptr;
     closure_on = false;
   }
 };
@@ -370,7 +367,7 @@ int lb_step(lb_handle h, long long n) {
   const StepArgs a = h->args();
   for (long long k = 0; k < n; ++k) {
     hipError_t e = h->closure_on
-                       ? lbrr::closure_step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], h->cl_m, a,
+                       ? lbrr::closure_step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a,
                                             h->cl_packed, h->cl_params, h->cl_norm, h->stream)
                        : h->ops->step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
@@ -552,7 +549,6 @@ int lb_set_closure(lb_handle h, const float* params, const float* norm, int enab
     HIP_TRY(hipMalloc(&h->cl_params, sizeof(float) * lbrr::kMlpNParam), "hipMalloc closure params");
     HIP_TRY(hipMalloc(&h->cl_norm, sizeof(float) * lbrr::kMlpNNorm), "hipMalloc closure norm");
     HIP_TRY(hipMalloc(&h->cl_packed, sizeof(uint16_t) * lbrr::kMlpNPacked), "hipMalloc closure weights");
-    HIP_TRY(hipMalloc(&h->cl_m, sizeof(float) * 3 * size_t(h->nodes())), "hipMalloc closure moments");
   }
   HIP_TRY(hipMemcpyAsync(h->cl_params, params, sizeof(float) * lbrr::kMlpNParam, hipMemcpyDeviceToDevice, h->stream),
           "copy closure params");

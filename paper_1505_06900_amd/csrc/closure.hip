@@ -63,21 +63,31 @@ __global__ void __launch_bounds__(256) k_coarsen(const T* __restrict__ rho, cons
   pi1_c[2 * nc + c] = alpha * vyy * inv + beta * tyy;
 }
 
-// (rho - rho0, u_x, u_y) of every node of a stored D2Q9 state (compact [3][ny][nx]).
+// (rho - rho0, u_x, u_y) of the stored D2Q9 state at element offset off.
 template <class S>
-__global__ void __launch_bounds__(256) k_node_moments(const S* __restrict__ src, StepArgs a, float* __restrict__ m) {
+__device__ __forceinline__ void node_moments3(const S* __restrict__ src, const StepArgs& a, int64_t off,
+                                              float (&v)[3]) {
   using R = typename Prec<S>::R;
-  const int64_t nodes = int64_t(a.nx) * a.ny;
-  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (n >= nodes) return;
-  const int64_t off = node_offset(a, uint32_t(n));
   R f[9];
   sfor<0, 9>([&](auto I) { f[I] = R(src[int64_t(I) * a.si + off]); });
   const Moments<R> mo = raw_moments<D2Q9, R>(f);
   const Hydro<R> h = hydro<D2Q9, R>(mo, R(a.rho0));
-  m[n] = float(h.drho);
-  m[nodes + n] = float(h.ux);
-  m[2 * nodes + n] = float(h.uy);
+  v[0] = float(h.drho);
+  v[1] = float(h.ux);
+  v[2] = float(h.uy);
+}
+
+// (rho - rho0, u_x, u_y) of every node of a stored D2Q9 state (compact [3][ny][nx]).
+template <class S>
+__global__ void __launch_bounds__(256) k_node_moments(const S* __restrict__ src, StepArgs a, float* __restrict__ m) {
+  const int64_t nodes = int64_t(a.nx) * a.ny;
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nodes) return;
+  float v[3];
+  node_moments3<S>(src, a, node_offset(a, uint32_t(n)), v);
+  m[n] = v[0];
+  m[nodes + n] = v[1];
+  m[2 * nodes + n] = v[2];
 }
 
 // Pull the 9 pre-collision deviations of node (x, y) from a stored state.
@@ -161,32 +171,37 @@ __device__ __forceinline__ void load_constants(const float* __restrict__ params,
   }
 }
 
-// Forward pass of the 64 samples of a wave (sample s = lane s); every thread
-// of the block calls it (barriers inside).  The products are computed
-// transposed, features x samples (weights as the matrix-core A operand), so a
-// lane's result, four consecutive features of one sample, goes to the
-// sample's LDS row with one 8-byte write and is read back as the next layer's
-// operand with one 8-byte read.  feat: the lane's raw features; w: packed
-// weights in LDS; r0, r1: the wave's two activation regions; c: constants.
-__device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uint16_t* w, uint16_t* r0, uint16_t* r1,
-                                             const float* c, float (&out)[kOut]) {
+// Forward pass of a group of 64 samples shared by NW waves; every thread of
+// the block calls it (barriers inside).  Wave `part` (0..NW-1) of the group
+// computes every NW-th output tile of each layer; wave 0 holds the samples
+// (sample s = its lane s): it writes their features and reads their outputs.
+// The products are computed transposed, features x samples (weights as the
+// matrix-core A operand), so a lane's result, four consecutive features of
+// one sample, goes to the sample's LDS row with one 8-byte write and is read
+// back as the next layer's operand with one 8-byte read.  feat: the lane's raw
+// features (wave 0); w: packed weights in LDS; r0, r1: the group's two
+// activation regions; c: constants.
+template <int NW>
+__device__ __forceinline__ void forward_group(const float (&feat)[kIn], int part, const uint16_t* w, uint16_t* r0,
+                                              uint16_t* r1, const float* c, float (&out)[kOut]) {
   const int lane = threadIdx.x & 63, q = lane >> 4;
-  // standardised BF16 features, row = sample (stride kLd1, inputs 36..47 zero)
-  bf16x4* xr = reinterpret_cast<bf16x4*>(r0 + lane * kLd1);
+  if (part == 0) {  // standardised BF16 features, row = sample (stride kLd1, inputs 36..47 zero)
+    bf16x4* xr = reinterpret_cast<bf16x4*>(r0 + lane * kLd1);
 #pragma unroll
-  for (int k4 = 0; k4 < kInP / 4; ++k4) {
-    bf16x4 v;
+    for (int k4 = 0; k4 < kInP / 4; ++k4) {
+      bf16x4 v;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k = 4 * k4 + r;
-      v[r] = short(k < kIn ? to_bf16((feat[k] - c[kCMean + k]) * c[kCInv + k]) : uint16_t(0));
+      for (int r = 0; r < 4; ++r) {
+        const int k = 4 * k4 + r;
+        v[r] = short(k < kIn ? to_bf16((feat[k] - c[kCMean + k]) * c[kCInv + k]) : uint16_t(0));
+      }
+      xr[k4] = v;
     }
-    xr[k4] = v;
   }
   __syncthreads();
   // layer 1: H1 = gelu(W1 X + b1), 4 x 4 tiles (features j0, samples s0) -> r1
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
+  for (int t = part; t < 16; t += NW) {
     const int j0 = 16 * (t & 3), s0 = 16 * (t >> 2);
     f32x4 acc = {0, 0, 0, 0};
     acc = tile_kc<kInP>(w + kPW1, kLd1, r0, kLd1, j0, s0, acc);
@@ -199,7 +214,7 @@ __device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uin
   __syncthreads();
   // layer 2: H2 = gelu(W2 H1 + b2) -> r0
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
+  for (int t = part; t < 16; t += NW) {
     const int j0 = 16 * (t & 3), s0 = 16 * (t >> 2);
     f32x4 acc = {0, 0, 0, 0};
     acc = tile_kc<kH>(w + kPW2, kLdH, r1, kLdH, j0, s0, acc);
@@ -213,7 +228,7 @@ __device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uin
   // layer 3: Y = W3 H2 + b3 (rows 0..2 of one 16-row tile), FP32 -> r1 as [64][4]
   float* ys = reinterpret_cast<float*>(r1);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = part; t < 4; t += NW) {
     const int s0 = 16 * t;
     f32x4 acc = {0, 0, 0, 0};
     acc = tile_kc<kH>(w + kPW3, kLdH, r0, kLdH, 0, s0, acc);
@@ -223,8 +238,10 @@ __device__ __forceinline__ void forward_wave(const float (&feat)[kIn], const uin
     }
   }
   __syncthreads();
+  if (part == 0) {
 #pragma unroll
-  for (int o = 0; o < kOut; ++o) out[o] = ys[lane * 4 + o] * c[kCYStd + o] + c[kCYMean + o];
+    for (int o = 0; o < kOut; ++o) out[o] = ys[lane * 4 + o] * c[kCYStd + o] + c[kCYMean + o];
+  }
   __syncthreads();
 }
 
@@ -248,7 +265,7 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_mlp_infer(const float* __r
   for (int k = 0; k < kIn; ++k) feat[k] = x[sc * kIn + k];
   __syncthreads();
   float out[kOut];
-  forward_wave(feat, w, reg[wave][0], reg[wave][1], cst, out);
+  forward_group<1>(feat, 0, w, reg[wave][0], reg[wave][1], cst, out);
   if (s < n)
     for (int o = 0; o < kOut; ++o) y[s * kOut + o] = out[o];
 }
@@ -500,32 +517,61 @@ __global__ void __launch_bounds__(256) k_pack(const float* __restrict__ params, 
 
 // ---------------------------------------------------------------------------
 // Fused coarse D2Q9 step with the closure: pull, moments, features, MLP on the
-// matrix cores (64 nodes per wave), a1^(2) += predicted correction, recursion
-// and reconstruction, store.  Every lane runs the MLP; lanes past the row end
-// use a wrapped node and do not store.
+// matrix cores, a1^(2) += predicted correction, recursion and reconstruction,
+// store.  A block handles 64 nodes of a row: wave 0 pulls and later collides
+// (one node per lane; lanes past the row end use a wrapped node and do not
+// store) while waves 1-3 compute (rho - rho0, u) of the stored state on rows
+// y-1, y, y+1 (64 + 2 nodes each) into LDS for the neighbour features; then
+// all four waves share the MLP tiles, so a 256^2 grid keeps four waves per
+// SIMD busy.
+constexpr int kClosureNW = 4;
+
 template <int N, class S>
-__global__ void __launch_bounds__(64 * kInferWaves) k_step_closure(const S* __restrict__ src, S* __restrict__ dst,
-                                                                   const float* __restrict__ m, StepArgs a,
-                                                                   const uint16_t* __restrict__ packed,
-                                                                   const float* __restrict__ params,
-                                                                   const float* __restrict__ norm) {
+__global__ void __launch_bounds__(64 * kClosureNW) k_step_closure(const S* __restrict__ src, S* __restrict__ dst, StepArgs a,
+                                                                  const uint16_t* __restrict__ packed,
+                                                                  const float* __restrict__ params,
+                                                                  const float* __restrict__ norm) {
   using R = typename Prec<S>::R;
   __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
-  __shared__ __attribute__((aligned(16))) uint16_t reg[kInferWaves][2][kRegion];
+  __shared__ __attribute__((aligned(16))) uint16_t reg[2][kRegion];
   __shared__ __attribute__((aligned(16))) float cst[kNConst];
-  load_weights<64 * kInferWaves>(packed, w);
+  __shared__ float nb[3][66][3];  // (rho - rho0, u) of rows y-1, y, y+1 at x0-1 .. x0+64
+  load_weights<64 * kClosureNW>(packed, w);
   load_constants(params, norm, cst);
-  const int xr = blockIdx.x * blockDim.x + threadIdx.x;
+  const int part = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int x0 = blockIdx.x * 64, xr = x0 + lane;
   const bool active = xr < a.nx;
   const int x = active ? xr : xr % a.nx;
   const int y = blockIdx.y;
   R f[9];
-  pull9<S, R>(src, a, x, y, f);
-  float feat[kIn];
-  features36<R>(f, m, a, x, y, feat);
+  if (part == 0) {
+    pull9<S, R>(src, a, x, y, f);
+  } else if (part <= 3) {
+    const int yy = (y + part - 2 + a.ny) % a.ny;
+    for (int k = lane; k < 66; k += 64) {
+      const int xx = ((x0 - 1 + k) % a.nx + a.nx) % a.nx;
+      float v[3];
+      node_moments3<S>(src, a, int64_t(yy) * a.sy + xx, v);
+      nb[part - 1][k][0] = v[0];
+      nb[part - 1][k][1] = v[1];
+      nb[part - 1][k][2] = v[2];
+    }
+  }
   __syncthreads();
+  float feat[kIn];
+  if (part == 0) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) feat[i] = float(f[i]);
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) feat[9 + 3 * (3 * dy + dx) + c] = nb[dy][lane + dx][c];
+  }
   float d[kOut];
-  forward_wave(feat, w, reg[threadIdx.x >> 6][0], reg[threadIdx.x >> 6][1], cst, d);
+  forward_group<kClosureNW>(feat, part, w, reg[0], reg[1], cst, d);
+  if (part != 0) return;
   const Moments<R> mo = raw_moments<D2Q9, R>(f);
   Hydro<R> h = hydro<D2Q9, R>(mo, R(a.rho0));
   h.axx += R(d[0]);
@@ -541,25 +587,22 @@ __global__ void __launch_bounds__(64 * kInferWaves) k_step_closure(const S* __re
 }
 
 template <class S>
-hipError_t step_closure_s(int order, const void* src, void* dst, float* m, const StepArgs& a,
-                          const uint16_t* packed, const float* params, const float* norm, hipStream_t s) {
-  const int64_t nodes = int64_t(a.nx) * a.ny;
-  hipLaunchKernelGGL((k_node_moments<S>), dim3(unsigned((nodes + 255) / 256)), dim3(256), 0, s,
-                     static_cast<const S*>(src), a, m);
-  const int bx = 64 * kInferWaves;
-  dim3 grid((a.nx + bx - 1) / bx, a.ny, 1);
+hipError_t step_closure_s(int order, const void* src, void* dst, const StepArgs& a, const uint16_t* packed,
+                          const float* params, const float* norm, hipStream_t s) {
+  dim3 grid((a.nx + 63) / 64, a.ny, 1);
+  const int bx = 64 * kClosureNW;
   switch (order) {
     case 2:
       hipLaunchKernelGGL((k_step_closure<2, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
-                         m, a, packed, params, norm);
+                         a, packed, params, norm);
       break;
     case 3:
       hipLaunchKernelGGL((k_step_closure<3, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
-                         m, a, packed, params, norm);
+                         a, packed, params, norm);
       break;
     case 4:
       hipLaunchKernelGGL((k_step_closure<4, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
-                         m, a, packed, params, norm);
+                         a, packed, params, norm);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -579,12 +622,12 @@ hipError_t features_s(const void* src, float* m, const StepArgs& a, const double
 
 }  // namespace
 
-hipError_t closure_step(int order, int storage, const void* src, void* dst, float* m, const StepArgs& a,
+hipError_t closure_step(int order, int storage, const void* src, void* dst, const StepArgs& a,
                         const uint16_t* packed, const float* params, const float* norm, hipStream_t s) {
   switch (storage) {
-    case 0: return step_closure_s<double>(order, src, dst, m, a, packed, params, norm, s);
-    case 1: return step_closure_s<float>(order, src, dst, m, a, packed, params, norm, s);
-    case 2: return step_closure_s<_Float16>(order, src, dst, m, a, packed, params, norm, s);
+    case 0: return step_closure_s<double>(order, src, dst, a, packed, params, norm, s);
+    case 1: return step_closure_s<float>(order, src, dst, a, packed, params, norm, s);
+    case 2: return step_closure_s<_Float16>(order, src, dst, a, packed, params, norm, s);
   }
   return hipErrorInvalidValue;
 }

@@ -14,7 +14,7 @@ constexpr int kMlpNNorm = 78;     // x_mean 36, x_std 36, y_mean 3, y_std 3
 constexpr int kMlpNPacked = 8768; // BF16 weights, padded rows (layout in mlp.hpp)
 constexpr int kMlpIn = 36;
 
-hipError_t closure_step(int order, int storage, const void* src, void* dst, float* m, const StepArgs& a,
+hipError_t closure_step(int order, int storage, const void* src, void* dst, const StepArgs& a,
                         const uint16_t* packed, const float* params, const float* norm, hipStream_t s);
 hipError_t closure_features(int storage, const void* src, float* m, const StepArgs& a, const double* a_target,
                             double plain_weight, float* feat, float* lab, hipStream_t s);
