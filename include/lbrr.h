@@ -120,6 +120,21 @@ int lb_init_fields(lb_handle h, const void* rho, const void* u, const void* pi1,
  * the failing step). */
 int lb_step(lb_handle h, long long n);
 
+/* Resting no-slip walls (u = 0) on the first and last node of each axis in
+ * the mask `walls` (bit 0 x, bit 1 y, bit 2 z; 0 = fully periodic, the
+ * default); the other axes stay periodic.  The regularised Dirichlet
+ * boundary of Sec. 3.7: at a wall node the populations whose source lies
+ * outside the box are unknown; an unknown one takes the off-equilibrium part
+ * of its opposite if that one is known (here f_i = f_opp), else its
+ * equilibrium value (edges and corners); rho is the zeroth moment of the
+ * completed set, a1^(2) its second moment minus rho c_s^2 I, and the node
+ * collides with (rho, u = 0, a1^(2)).  Velocities given to lb_init_fields on
+ * wall nodes should be 0.  A walled axis needs at least 3 nodes; population
+ * storage only, no learned closure (LB_ERR_UNSUPPORTED otherwise).
+ * lb_enstrophy uses one-sided differences on the walls.  Takes effect at the
+ * next lb_step. */
+int lb_set_walls(lb_handle h, int walls);
+
 /* Stability check interval k for lb_step (0 = never, the default). */
 int lb_set_check_interval(lb_handle h, long long k);
 
@@ -138,8 +153,9 @@ int lb_moments(lb_handle h, void* rho, void* u, void* pi1, int dtype, int on_dev
 int lb_reduce(lb_handle h, double out[5]);
 
 /* Volume mean of |omega|^2 / 2, omega = curl u by second-order periodic
- * central differences, accumulated in FP64 (the enstrophy of Sec. 4.1,
- * normalised by the number of nodes).  Synchronises the stream. */
+ * central differences (second-order one-sided on walls, lb_set_walls),
+ * accumulated in FP64 (the enstrophy of Sec. 4.1, normalised by the number
+ * of nodes).  Synchronises the stream. */
 int lb_enstrophy(lb_handle h, double* out);
 
 /* Copy the stored post-collision deviations f_i - w_i rho0 out of / into the

@@ -109,6 +109,13 @@ class Simulation:
         check(_lib.load().lb_step(self.handle, int(n)))
         return self
 
+    def set_walls(self, x=False, y=False, z=False):
+        """Resting no-slip walls on the first and last node of the flagged axes (lb_set_walls)."""
+        mask = (1 if x else 0) | (2 if y else 0) | (4 if z else 0)
+        check(_lib.load().lb_set_walls(self.handle, mask))
+        self.walls = (bool(x), bool(y), bool(z))
+        return self
+
     def set_check_interval(self, k):
         check(_lib.load().lb_set_check_interval(self.handle, int(k)))
 

@@ -33,6 +33,7 @@ SIGNATURES = {
     "lb_init_fields": (_I, [_VP, _VP, _VP, _VP, _I, _I]),
     "lb_step": (_I, [_VP, _LL]),
     "lb_set_check_interval": (_I, [_VP, _LL]),
+    "lb_set_walls": (_I, [_VP, _I]),
     "lb_moments": (_I, [_VP, _VP, _VP, _VP, _I, _I]),
     "lb_reduce": (_I, [_VP, ctypes.POINTER(_D)]),
     "lb_enstrophy": (_I, [_VP, ctypes.POINTER(_D)]),

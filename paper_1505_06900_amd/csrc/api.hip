@@ -94,6 +94,7 @@ struct lb_ctx {
   bool ready = false;
   long long steps = 0;
   long long check_every = 0;
+  int walls = 0;  // bit 0 x, bit 1 y, bit 2 z: resting no-slip walls on the first and last node
   double* partials = nullptr;
   int nblocks = 0;
   double* dev_out = nullptr;
@@ -313,6 +314,18 @@ int lb_set_stream(lb_handle h, void* hip_stream) {
   return LB_OK;
 }
 
+int lb_set_walls(lb_handle h, int walls) {
+  if (int r = check_handle(h)) return r;
+  if (walls < 0 || walls > 7) return fail(LB_ERR_INVALID_ARG, "walls must be a mask of bits 0 (x), 1 (y), 2 (z)");
+  if ((walls & 4) && h->d() == 2) return fail(LB_ERR_INVALID_ARG, "a 2D lattice has no z walls");
+  const int dims[3] = {h->nx, h->ny, h->nz};
+  for (int k = 0; k < 3; ++k)
+    if ((walls >> k & 1) && dims[k] < 3) return fail(LB_ERR_INVALID_ARG, "a walled axis needs at least 3 nodes");
+  if (walls && h->moment()) return fail(LB_ERR_UNSUPPORTED, "walls need population storage");
+  h->walls = walls;
+  return LB_OK;
+}
+
 int lb_set_check_interval(lb_handle h, long long k) {
   if (int r = check_handle(h)) return r;
   if (k < 0) return fail(LB_ERR_INVALID_ARG, "check interval must be >= 0");
@@ -364,12 +377,18 @@ int lb_step(lb_handle h, long long n) {
   if (n < 0) return fail(LB_ERR_INVALID_ARG, "n must be >= 0");
   if (!h->ready) return fail(LB_ERR_STATE, "lb_step before lb_init_fields / lb_set_populations");
   if (h->closure_on && h->moment()) return fail(LB_ERR_UNSUPPORTED, "the learned closure needs population storage");
+  if (h->walls && (h->moment() || h->closure_on))
+    return fail(LB_ERR_UNSUPPORTED, "walls need population storage and no closure");
   const StepArgs a = h->args();
   for (long long k = 0; k < n; ++k) {
-    hipError_t e = h->closure_on
-                       ? lbrr::closure_step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a,
-                                            h->cl_packed, h->cl_params, h->cl_norm, h->stream)
-                       : h->ops->step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->stream);
+    hipError_t e;
+    if (h->closure_on)
+      e = lbrr::closure_step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->cl_packed, h->cl_params,
+                             h->cl_norm, h->stream);
+    else if (h->walls)
+      e = h->ops->step_walls(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->walls, h->stream);
+    else
+      e = h->ops->step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     h->cur ^= 1;
     ++h->steps;
@@ -429,7 +448,8 @@ int lb_enstrophy(lb_handle h, double* out) {
   if (!h->vel) HIP_TRY(hipMalloc(&h->vel, sizeof(double) * size_t(h->nodes()) * h->d()), "hipMalloc velocity");
   hipError_t e = h->ops->velocity(h->storage, h->buf[h->cur], h->vel, h->args(), h->stream);
   if (e == hipSuccess)
-    e = lbrr::launch_enstrophy(h->vel, h->d(), h->nx, h->ny, h->nz, h->partials, h->nblocks, h->dev_out, h->stream);
+    e = lbrr::launch_enstrophy(h->vel, h->d(), h->nx, h->ny, h->nz, h->walls, h->partials, h->nblocks, h->dev_out,
+                               h->stream);
   if (e != hipSuccess) return hip_fail(e, "enstrophy kernels");
   double s = 0.0;
   HIP_TRY(hipMemcpyAsync(&s, h->dev_out, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy enstrophy");

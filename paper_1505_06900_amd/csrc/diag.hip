@@ -29,42 +29,49 @@ __device__ __forceinline__ void block_sum_store1(double v, double* __restrict__ 
   }
 }
 
-// Per-block partial sums of |omega|^2 / 2, omega by second-order central
-// differences on the periodic lattice (2D: the scalar w_z).
+// Derivative along one axis of a field at node n (index stride st, position i
+// of n >= 0 along an axis of n_ nodes): second-order central differences,
+// periodic; on a walled axis the first and last node use the second-order
+// one-sided formulas (-3 a0 + 4 a1 - a2)/2 and (3 a_n-1 - 4 a_n-2 + a_n-3)/2.
+__device__ __forceinline__ double axis_derivative(const double* __restrict__ a, int64_t n, int64_t st, int i, int n_,
+                                                  bool walled) {
+  if (walled && i == 0) return 0.5 * (-3.0 * a[n] + 4.0 * a[n + st] - a[n + 2 * st]);
+  if (walled && i == n_ - 1) return 0.5 * (3.0 * a[n] - 4.0 * a[n - st] + a[n - 2 * st]);
+  const int64_t p = (i + 1 == n_) ? n - int64_t(i) * st : n + st;
+  const int64_t m = (i == 0) ? n + int64_t(n_ - 1) * st : n - st;
+  return 0.5 * (a[p] - a[m]);
+}
+
+// Per-block partial sums of |omega|^2 / 2, omega by second-order differences
+// (periodic, one-sided on the walls of `walls`: bit 0 x, 1 y, 2 z); 2D: w_z.
 __global__ void __launch_bounds__(kReduceBlock) k_enstrophy(const double* __restrict__ u, int d, int nx, int ny,
-                                                            int nz, int64_t per_block, double* __restrict__ partials) {
+                                                            int nz, int walls, int64_t per_block,
+                                                            double* __restrict__ partials) {
   const int64_t nodes = int64_t(nx) * ny * nz;
   const int64_t begin = int64_t(blockIdx.x) * per_block;
   const int64_t end = begin + per_block < nodes ? begin + per_block : nodes;
   const double* ux = u;
   const double* uy = u + nodes;
   const double* uz = u + 2 * nodes;
+  const bool wx = walls & 1, wy = walls & 2, wz = walls & 4;
+  const int64_t sxy = int64_t(nx) * ny;
   double acc = 0.0;
   for (int64_t n = begin + threadIdx.x; n < end; n += kReduceBlock) {
     const int x = int(n % nx);
     const int y = int((n / nx) % ny);
-    const int z = int(n / (int64_t(nx) * ny));
-    const int64_t row = n - x;
-    const int64_t xp = row + (x + 1 == nx ? 0 : x + 1), xm = row + (x == 0 ? nx - 1 : x - 1);
-    const int64_t plane = n - int64_t(y) * nx;
-    const int64_t yp = plane + int64_t(y + 1 == ny ? 0 : y + 1) * nx;
-    const int64_t ym = plane + int64_t(y == 0 ? ny - 1 : y - 1) * nx;
-    const int64_t sxy = int64_t(nx) * ny;
-    const int64_t vol = n - int64_t(z) * sxy;
-    const int64_t zp = vol + int64_t(z + 1 == nz ? 0 : z + 1) * sxy;
-    const int64_t zm = vol + int64_t(z == 0 ? nz - 1 : z - 1) * sxy;
-    const double duy_dx = 0.5 * (uy[xp] - uy[xm]);
-    const double dux_dy = 0.5 * (ux[yp] - ux[ym]);
+    const int z = int(n / sxy);
+    const double duy_dx = axis_derivative(uy, n, 1, x, nx, wx);
+    const double dux_dy = axis_derivative(ux, n, nx, y, ny, wy);
     if (d == 2) {
       const double w = duy_dx - dux_dy;
       acc += 0.5 * w * w;
     } else {
-      const double duz_dy = 0.5 * (uz[yp] - uz[ym]);
-      const double duy_dz = 0.5 * (uy[zp] - uy[zm]);
-      const double dux_dz = 0.5 * (ux[zp] - ux[zm]);
-      const double duz_dx = 0.5 * (uz[xp] - uz[xm]);
-      const double wx = duz_dy - duy_dz, wy = dux_dz - duz_dx, wz = duy_dx - dux_dy;
-      acc += 0.5 * (wx * wx + wy * wy + wz * wz);
+      const double duz_dy = axis_derivative(uz, n, nx, y, ny, wy);
+      const double duy_dz = axis_derivative(uy, n, sxy, z, nz, wz);
+      const double dux_dz = axis_derivative(ux, n, sxy, z, nz, wz);
+      const double duz_dx = axis_derivative(uz, n, 1, x, nx, wx);
+      const double wxv = duz_dy - duy_dz, wyv = dux_dz - duz_dx, wzv = duy_dx - dux_dy;
+      acc += 0.5 * (wxv * wxv + wyv * wyv + wzv * wzv);
     }
   }
   block_sum_store1(acc, partials);
@@ -87,11 +94,12 @@ __global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32
 
 }  // namespace
 
-hipError_t launch_enstrophy(const double* u, int d, int nx, int ny, int nz, double* partials, int nblocks,
+hipError_t launch_enstrophy(const double* u, int d, int nx, int ny, int nz, int walls, double* partials, int nblocks,
                             double* out, hipStream_t s) {
   const int64_t nodes = int64_t(nx) * ny * nz;
   const int64_t per_block = (nodes + nblocks - 1) / nblocks;
-  hipLaunchKernelGGL(k_enstrophy, dim3(nblocks), dim3(kReduceBlock), 0, s, u, d, nx, ny, nz, per_block, partials);
+  hipLaunchKernelGGL(k_enstrophy, dim3(nblocks), dim3(kReduceBlock), 0, s, u, d, nx, ny, nz, walls, per_block,
+                     partials);
   hipLaunchKernelGGL(k_final1, dim3(1), dim3(kReduceBlock), 0, s, partials, nblocks, out);
   return hipGetLastError();
 }

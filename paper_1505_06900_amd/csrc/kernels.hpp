@@ -78,6 +78,102 @@ __global__ void __launch_bounds__(256) k_step(const S* __restrict__ src, S* __re
   sfor<0, L::Q>([&](auto I) { __builtin_nontemporal_store(to_store<S, R>(f[I]), out + int64_t(I) * a.si); });
 }
 
+// ---------------------------------------------------------------------------
+// The same step with resting no-slip walls on the first and last node of the
+// axes flagged in `walls` (bit 0 x, bit 1 y, bit 2 z): the regularised
+// Dirichlet boundary of Sec. 3.7 with u_bc = 0.  At a wall node a population
+// whose source lies outside the box is unknown: it takes the off-equilibrium
+// part of its opposite (for u = 0 and w_i = w_opp: d_i = d_opp) if that one is
+// known, else the equilibrium value (d_i = w_i (rho - rho0)); rho - rho0 then
+// follows from the zeroth moment of the completed set,
+//   (rho - rho0) (1 - sum_buried w_i) = sum_known d_i + sum_bounced d_opp,
+// a1^(2) is its second moment minus (rho - rho0) c_s^2 I (u = 0), and the node
+// collides with (rho, u = 0, a1^(2)), i.e. its populations are replaced by the
+// regularised f0 + f1 before the collision.  Other nodes are unchanged.
+// Population Q-1-i moves along -xi_i (canonical order of every lattice here).
+template <class L>
+constexpr bool opposite_is_reversed() {
+  for (int i = 0; i < L::Q; ++i)
+    if (L::cx(L::Q - 1 - i) != -L::cx(i) || L::cy(L::Q - 1 - i) != -L::cy(i) || L::cz(L::Q - 1 - i) != -L::cz(i))
+      return false;
+  return true;
+}
+
+template <class L, int N, class S>
+__global__ void __launch_bounds__(256) k_step_walls(const S* __restrict__ src, S* __restrict__ dst, StepArgs a,
+                                                    int walls) {
+  static_assert(opposite_is_reversed<L>(), "population order");
+  using R = typename Prec<S>::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.nx) return;
+  const int y = blockIdx.y, z = blockIdx.z;
+  const int xm = (x == 0) ? a.nx - 1 : x - 1;
+  const int xp = (x == a.nx - 1) ? 0 : x + 1;
+  const int ym = (y == 0) ? a.ny - 1 : y - 1;
+  const int yp = (y == a.ny - 1) ? 0 : y + 1;
+  const int zm = (z == 0) ? a.nz - 1 : z - 1;
+  const int zp = (z == a.nz - 1) ? 0 : z + 1;
+  R f[L::Q];  // sources outside a walled box wrap around here and are replaced below
+  sfor<0, L::Q>([&](auto I) {
+    constexpr int cx = L::cx(I), cy = L::cy(I), cz = L::cz(I);
+    const int xs = (cx == 1) ? xm : ((cx == -1) ? xp : x);
+    const int ys = (cy == 1) ? ym : ((cy == -1) ? yp : y);
+    const int zs = (cz == 1) ? zm : ((cz == -1) ? zp : z);
+    const S* row = src + int64_t(I) * a.si + int64_t(zs) * a.sz + int64_t(ys) * a.sy;
+    f[I] = R(row[xs]);
+  });
+  // sides of the box this node lies on: -1 (first node), +1 (last node), 0
+  const int sx = (walls & 1) ? (x == 0 ? -1 : (x == a.nx - 1 ? 1 : 0)) : 0;
+  const int sy = (walls & 2) ? (y == 0 ? -1 : (y == a.ny - 1 ? 1 : 0)) : 0;
+  const int sz = (L::D == 3 && (walls & 4)) ? (z == 0 ? -1 : (z == a.nz - 1 ? 1 : 0)) : 0;
+  if (sx == 0 && sy == 0 && sz == 0) {
+    collide<L, N, R>(f, R(a.rho0), R(a.omega1));
+  } else {
+    // population with velocity c comes from outside iff some side s != 0 has c = -s
+    auto from_outside = [&](int cx, int cy, int cz) {
+      return (sx != 0 && cx == -sx) || (sy != 0 && cy == -sy) || (sz != 0 && cz == -sz);
+    };
+    R sd = R(0), wb = R(0);
+    sfor<0, L::Q>([&](auto I) {
+      constexpr int cx = L::cx(I), cy = L::cy(I), cz = L::cz(I);
+      constexpr int O = L::Q - 1 - int(I);  // opposite velocity
+      if (!from_outside(cx, cy, cz)) sd = sd + f[I];
+      else if (!from_outside(-cx, -cy, -cz)) sd = sd + f[O];
+      else wb = wb + R(L::w(I));
+    });
+    const R drho = sd / (R(1) - wb);
+    R g[L::Q];
+    sfor<0, L::Q>([&](auto I) {
+      constexpr int cx = L::cx(I), cy = L::cy(I), cz = L::cz(I);
+      constexpr int O = L::Q - 1 - int(I);
+      if (!from_outside(cx, cy, cz)) g[I] = f[I];
+      else if (!from_outside(-cx, -cy, -cz)) g[I] = f[O];
+      else g[I] = R(L::w(I)) * drho;
+    });
+    const Moments<R> m = raw_moments<L, R>(g);
+    constexpr R cs2 = R(kCs2);
+    Hydro<R> h;
+    h.drho = drho;
+    h.rho = R(a.rho0) + drho;
+    h.ux = h.uy = h.uz = h.jx = h.jy = h.jz = R(0);
+    h.axx = m.pxx - drho * cs2;
+    h.ayy = m.pyy - drho * cs2;
+    h.axy = m.pxy;
+    if constexpr (L::D == 3) {
+      h.azz = m.pzz - drho * cs2;
+      h.axz = m.pxz;
+      h.ayz = m.pyz;
+    } else {
+      h.azz = h.axz = h.ayz = R(0);
+    }
+    R C[3][3][3];
+    coefficients<L, N, R>(h, R(a.omega1), C);
+    reconstruct<L, N, R>(C, f);
+  }
+  S* out = dst + int64_t(z) * a.sz + int64_t(y) * a.sy + x;
+  sfor<0, L::Q>([&](auto I) { __builtin_nontemporal_store(to_store<S, R>(f[I]), out + int64_t(I) * a.si); });
+}
+
 // Copy between the internal layout and compact SoA [q][node].
 template <class L, class S>
 __global__ void __launch_bounds__(256) k_repack(const S* __restrict__ src, S* __restrict__ dst, StepArgs a,
@@ -256,6 +352,15 @@ hipError_t launch_step(const void* src, void* dst, const StepArgs& a, hipStream_
   const int bx = a.nx >= 256 ? 256 : ((a.nx + 63) / 64) * 64;
   dim3 grid((a.nx + bx - 1) / bx, a.ny, a.nz);
   hipLaunchKernelGGL((k_step<L, N, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst), a);
+  return hipGetLastError();
+}
+
+template <class L, int N, class S>
+hipError_t launch_step_walls(const void* src, void* dst, const StepArgs& a, int walls, hipStream_t s) {
+  const int bx = a.nx >= 256 ? 256 : ((a.nx + 63) / 64) * 64;
+  dim3 grid((a.nx + bx - 1) / bx, a.ny, a.nz);
+  hipLaunchKernelGGL((k_step_walls<L, N, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
+                     a, walls);
   return hipGetLastError();
 }
 

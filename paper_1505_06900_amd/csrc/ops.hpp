@@ -35,6 +35,9 @@ struct LatticeOps {
   hipError_t (*repack)(int storage, const void* src, void* dst, bool to_compact, const StepArgs& a, hipStream_t s);
   // moment storage: post-collision deviations of the state, compact SoA [q][nz][ny][nx]
   hipError_t (*mpopulations)(int order, int storage, const void* src, void* dst, const StepArgs& a, hipStream_t s);
+  // population storage with resting walls on the axes of `walls` (bit 0 x, 1 y, 2 z)
+  hipError_t (*step_walls)(int order, int storage, const void* src, void* dst, const StepArgs& a, int walls,
+                           hipStream_t s);
 };
 
 // Storage kinds (values of lb_storage): populations 0 FP64, 1 FP32, 2 FP16;
@@ -46,7 +49,7 @@ const LatticeOps& ops_d3q19();
 const LatticeOps& ops_d3q27();
 
 // diagnostics kernels (diag.hip)
-hipError_t launch_enstrophy(const double* u, int d, int nx, int ny, int nz, double* partials, int nblocks,
+hipError_t launch_enstrophy(const double* u, int d, int nx, int ny, int nz, int walls, double* partials, int nblocks,
                             double* out, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t n, hipStream_t s);
 

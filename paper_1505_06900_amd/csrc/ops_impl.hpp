@@ -32,6 +32,18 @@ hipError_t mpop_by_order(int order, const void* src, void* dst, const StepArgs& 
   return hipErrorInvalidValue;
 }
 
+template <class L, class S>
+hipError_t step_walls_by_order(int order, const void* src, void* dst, const StepArgs& a, int walls, hipStream_t s) {
+  switch (order) {
+    case 2: return launch_step_walls<L, 2, S>(src, dst, a, walls, s);
+    case 3: return launch_step_walls<L, 3, S>(src, dst, a, walls, s);
+    case 4: return launch_step_walls<L, 4, S>(src, dst, a, walls, s);
+    case 5: if constexpr (L::NMAX >= 5) return launch_step_walls<L, 5, S>(src, dst, a, walls, s); break;
+    case 6: if constexpr (L::NMAX >= 6) return launch_step_walls<L, 6, S>(src, dst, a, walls, s); break;
+  }
+  return hipErrorInvalidValue;
+}
+
 template <class L>
 struct OpsImpl {
   static hipError_t step(int order, int storage, const void* src, void* dst, const StepArgs& a, hipStream_t s) {
@@ -104,9 +116,18 @@ struct OpsImpl {
     }
     return hipErrorInvalidValue;
   }
+  static hipError_t step_walls(int order, int storage, const void* src, void* dst, const StepArgs& a, int walls,
+                               hipStream_t s) {
+    switch (storage) {
+      case 0: return step_walls_by_order<L, double>(order, src, dst, a, walls, s);
+      case 1: return step_walls_by_order<L, float>(order, src, dst, a, walls, s);
+      case 2: return step_walls_by_order<L, _Float16>(order, src, dst, a, walls, s);
+    }
+    return hipErrorInvalidValue;
+  }
   static const LatticeOps& table() {
     static const LatticeOps t = {L::Q, L::D, L::NMAX, &step, &init, &moments, &totals, &velocity, &repack,
-                                 &mpopulations};
+                                 &mpopulations, &step_walls};
     return t;
   }
 };
