@@ -5,10 +5,10 @@ density / velocity / stress fields (float64 numpy arrays, layout [d][z][y][x],
 x fastest) and raw random numbers.  Both sides (the FP64 oracle and the HIP
 library) build their own populations from these fields.
 
-Flow recipes stand in for the paper's benchmarks (the dipole-wall and jet cases
-need walls, sponges and inlets): periodic Taylor--Green vortices, a double
-shear layer, random divergence-free fields and decaying 2D turbulence, at the
-Reynolds / Mach numbers of the workload table below.
+Flow recipes: the dipole of the paper's dipole-wall benchmark (Sec. 4.1, a
+closed box), and periodic stand-ins for its other flows: Taylor--Green
+vortices, a double shear layer, random divergence-free fields and decaying 2D
+turbulence, at the Reynolds / Mach numbers of the workload table below.
 """
 from __future__ import annotations
 
@@ -98,6 +98,26 @@ def random_vorticity2d(n, kmin, kmax, urms, seed):
     u = np.stack([ux, uy])
     u *= urms / math.sqrt(np.mean(np.sum(u**2, axis=0)))
     return np.ones((1, n, n)), u[:, None]
+
+
+def dipole(n_unit, omega_e=299.5286, r0=0.1, centres=((0.0, 0.1), (0.0, -0.1))):
+    """Dipole of the dipole-wall benchmark (Sec. 4.1, Eqs. dipole1 / dipole2) in the box [-1, 1]^2.
+
+    Nodes at x = -1 + i / n_unit, i = 0 .. 2 n_unit (the walls lie on the first and last node).
+    Returns the velocity in the paper's dimensionless units, u (2, 1, m, m), m = 2 n_unit + 1,
+    exactly 0 on the wall nodes, and the node coordinate x (m,)."""
+    m = 2 * n_unit + 1
+    x = -1.0 + np.arange(m, dtype=float) / n_unit
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    (x1, y1), (x2, y2) = centres
+    e1 = np.exp(-((X - x1) ** 2 + (Y - y1) ** 2) / r0**2)
+    e2 = np.exp(-((X - x2) ** 2 + (Y - y2) ** 2) / r0**2)
+    ux = -0.5 * abs(omega_e) * (Y - y1) * e1 + 0.5 * abs(omega_e) * (Y - y2) * e2
+    uy = 0.5 * abs(omega_e) * (X - x1) * e1 - 0.5 * abs(omega_e) * (X - x2) * e2
+    u = np.stack([ux, uy])[:, None]
+    u[:, :, [0, -1], :] = 0.0
+    u[:, :, :, [0, -1]] = 0.0
+    return u, x
 
 
 def smooth_random(ncomp, shape, amp, seed, kmax=2):
