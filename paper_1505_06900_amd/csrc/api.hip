@@ -51,9 +51,9 @@ size_t elem_size(int storage) {
 }
 
 // z-planes per block of the moment-state step: each block rebuilds lz + 2
-// planes.  Fewer, shorter chunks measured faster on MI355X despite the extra
-// rebuilds (256^3 D3Q27 FP32: 36 GLUPS at 4, 25 at 8 and more); LBRR_MOM_LZ
-// overrides it.
+// planes.  Short chunks measured faster on MI355X despite the extra rebuilds
+// (256^3 D3Q27 FP32: 36 GLUPS at 4, 26 at 6, 24-25 at 8 to 16, with one to
+// three planes prefetched); LBRR_MOM_LZ overrides it.
 int moment_lz() {
   if (const char* e = std::getenv("LBRR_MOM_LZ")) {
     const int v = std::atoi(e);

@@ -40,6 +40,7 @@ template <class L>
 constexpr int kNM = (L::D == 3) ? 10 : 6;
 
 constexpr int kMX = 32;  // patch of rebuilt nodes per block: kMX x TY
+constexpr int kPrefetch = 2;  // planes of moments in flight ahead of the rebuild
 
 // Hydrodynamic state of a node from its stored moments m.
 template <class L, class R>
@@ -226,21 +227,27 @@ __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S
   } else {
     // The moments of a completed target plane are kept in registers and
     // stored at the start of the next iteration, next to the prefetch of the
-    // plane after: both then have a whole rebuild to complete before the
-    // wait at the end of the iteration.
+    // plane kPrefetch ahead: loads and stores then have one or more whole
+    // rebuilds to complete before they are waited for.
     const int z0 = bz * a.lz;
     const int z1 = (z0 + a.lz < a.nz) ? z0 + a.lz : a.nz;
     Moments<R> prev, cur, next;  // sums of target planes p-1, p, p+1
     clear(prev);
     clear(cur);
     clear(next);
-    R mn[NM];  // moments of the plane rebuilt next, loaded one iteration ahead
-    load(wrap(z0 - 1, a.nz), mn);
+    // Moments of the planes to rebuild, kPrefetch planes in flight: the loop
+    // is unrolled kPrefetch times so that buffer k always holds the planes
+    // pz = z0 - 1 + k (mod kPrefetch); a buffer is refilled with the plane
+    // kPrefetch further on as soon as its contents are taken.
+    R pre[kPrefetch][NM];
+    sfor<0, kPrefetch>([&](auto K) {
+      if (z0 - 1 + int(K) <= z1) load(wrap(z0 - 1 + int(K), a.nz), pre[K]);
+    });
     R out[NM];  // moments of target plane pz - 2, stored during iteration pz
-    for (int pz = z0 - 1; pz <= z1; ++pz) {
+    auto iteration = [&](int pz, R (&buf)[NM]) __attribute__((always_inline)) {
       R m[NM];
-      sfor<0, NM>([&](auto C) { m[C] = mn[C]; });
-      if (pz < z1) load(wrap(pz + 1, a.nz), mn);
+      sfor<0, NM>([&](auto C) { m[C] = buf[C]; });
+      if (pz + kPrefetch <= z1) load(wrap(pz + kPrefetch, a.nz), buf);
       if (inner && pz >= z0 + 2) put(pz - 2, out);
       rebuild(m);
       lds_barrier();
@@ -254,6 +261,11 @@ __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S
         clear(next);
       }
       lds_barrier();
+    };
+    for (int pz = z0 - 1; pz <= z1; pz += kPrefetch) {
+      sfor<0, kPrefetch>([&](auto K) {
+        if (pz + int(K) <= z1) iteration(pz + int(K), pre[K]);
+      });
     }
     if (inner) put(z1 - 1, out);
   }
