@@ -71,3 +71,32 @@ def test_dissipation_of_shear_mode_matches_navier_stokes_at_small_k():
         d = lsa.dissipation_kx("D2Q9", 4, tau, 1.0, [0.0, 0.0], np.array([k]))[0]
     hydro = np.sort(d)[-3:]  # three least damped modes: two sound, one shear
     np.testing.assert_allclose(hydro, -nu * k * k, rtol=2e-3)
+
+
+def _max_growth_3d(lat, N, tau, u, nk=16):
+    k = -np.pi + 2 * np.pi * np.arange(nk) / nk
+    KX, KY, KZ = np.meshgrid(k, k, k, indexing="ij")
+    lam = lsa.amplification_eigs(lat, N, tau, 1.0, np.asarray(u, float), KX, KY, KZ)
+    return float(np.log(np.abs(lam)).max())
+
+
+def test_d3q19_order4_is_unstable_at_rest_near_tau_one_half():
+    """Finding: with the Gram reading of D3Q19 (kept polynomials with a zero exponent), order 4
+    relaxes the xxyy, xxzz, yyzz moments, which the D3Q19 weights couple to the second-order
+    ones; at rest the model then has growing high-wavenumber modes for tau close to 1/2
+    (0.0285 per step at tau = 0.51), while orders 2 and 3 do not, and neither does D3Q27 at
+    order 4.  From tau = 0.55 on the rest state is stable again."""
+    g4 = _max_growth_3d("D3Q19", 4, 0.51, (0, 0, 0))
+    assert g4 == pytest.approx(0.0285, abs=2e-3)
+    assert _max_growth_3d("D3Q19", 3, 0.51, (0, 0, 0)) < TOL
+    assert _max_growth_3d("D3Q19", 2, 0.51, (0, 0, 0)) < TOL
+    assert _max_growth_3d("D3Q27", 4, 0.51, (0, 0, 0)) < TOL
+    assert _max_growth_3d("D3Q19", 4, 0.55, (0, 0, 0)) < TOL
+
+
+def test_d2q9_high_mach_threshold_of_the_shear_layer_workload():
+    """At the relaxation time of the Ma 0.5 double shear layer (tau = 0.677362) the order-4 D2Q9
+    model is stable at u = (0.40, 0) and unstable at (0.45, 0): local Mach numbers near 0.8,
+    which that flow reaches transiently."""
+    assert lsa.max_growth("D2Q9", 4, 0.677362, 1.0, np.array([0.40, 0.0]), nk=64) < TOL
+    assert lsa.max_growth("D2Q9", 4, 0.677362, 1.0, np.array([0.45, 0.0]), nk=64) > 0.05
