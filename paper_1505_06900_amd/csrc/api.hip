@@ -51,15 +51,24 @@ size_t elem_size(int storage) {
 }
 
 // z-planes per block of the moment-state step: each block rebuilds lz + 2
-// planes.  Short chunks measured faster on MI355X despite the extra rebuilds
-// (256^3 D3Q27 FP32: 36 GLUPS at 4, 26 at 6, 24-25 at 8 to 16, with one to
-// three planes prefetched); LBRR_MOM_LZ overrides it.
-int moment_lz() {
+// planes.  Short chunks measured faster on MI355X despite the extra rebuilds,
+// down to the point where the lz + 2 planes a chunk reads outgrow the
+// aggregate L2 (8 x 4 MiB).  Measured, D3Q27 FP32 (GLUPS at lz = 2 / 3 / 4):
+// 256^2 planes 30 / 34 / 36, 320^2 30 / 33 / 33, 256 x 512 30 / 32 / 24,
+// 384^2 30 / 28 / 25, 512^2 30 / 22 / 21, that is fast while the chunk reads
+// at most about 26 MB; so FP32 takes the largest lz <= 4 that stays within
+// 27 MB, and never less than 2.  FP64 (twice the bytes, half the arithmetic
+// rate) measured best at 4 at 256^3 and 384^3 (19-20 GLUPS, 16.5 at 2).
+// LBRR_MOM_LZ overrides the choice.
+int moment_lz(int64_t nx, int64_t ny, int nvalues, size_t es) {
   if (const char* e = std::getenv("LBRR_MOM_LZ")) {
     const int v = std::atoi(e);
     if (v >= 1) return v;
   }
-  return 4;
+  int lz = 4;
+  if (es == 4)
+    while (lz > 2 && double(lz + 2) * double(nx * ny) * nvalues * es > 27e6) --lz;
+  return lz;
 }
 
 // Extra bytes after each population plane (layouts 0 and 2).  Planes whose
@@ -121,7 +130,7 @@ struct lb_ctx {
     a.sz = sz;
     a.rho0 = rho0;
     a.omega1 = 1.0 - 1.0 / tau;
-    a.lz = moment_lz();
+    a.lz = moment() ? moment_lz(nx, ny, nvalues(), elem_size(storage)) : 1;
     return a;
   }
   void release() {

@@ -384,8 +384,11 @@ __global__ void __launch_bounds__(256) k_mpopulations(const S* __restrict__ src,
 // Patch rows: 16 for FP32 (a 55 KiB exchange), 8 for FP64 (the same bytes).
 // Measured on the 256^3 D3Q27 step (FP32, fields of a row together): 8, 16
 // and 32 rows within 6%; 4 z-planes per chunk best (36 GLUPS), 8 and more
-// 30% slower; handing XCDs blocks of neighbouring tiles lowered the L2-miss
-// traffic by half but not the time.
+// 30% slower (larger planes want shorter chunks: the host's choice of lz);
+// handing XCDs blocks of neighbouring tiles lowered the L2-miss traffic by
+// half but not the time, and so did dispatching the z-chunks of a tile next
+// to each other (24-27 GLUPS at 256^3 and 512^3 for lz = 2 to 32); padding
+// the z-planes off multiples of 64 KiB changed nothing.
 template <class L, int N, class S>
 hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream_t s) {
   constexpr int TY = sizeof(S) == 4 ? 16 : 8;
