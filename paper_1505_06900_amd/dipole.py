@@ -25,8 +25,11 @@ RE = 2500.0
 REFERENCE_PEAKS = (3313.0, 1418.0)
 
 
-def lattice_parameters(n_unit):
-    u_lb = 0.01 * 125.0 / n_unit
+def lattice_parameters(n_unit, u_lb=None):
+    """(U_lb, nu, tau) at N nodes per unit length: U_lb = 0.01 * 125 / N unless given (the
+    constant-Mach runs of Sec. 4.1 keep U_lb fixed and let the viscosity follow Re)."""
+    if u_lb is None:
+        u_lb = 0.01 * 125.0 / n_unit
     nu = u_lb * n_unit / RE
     return u_lb, nu, 3.0 * nu + 0.5
 
@@ -71,14 +74,16 @@ def kinetic_energy(u, u_lb):
     return float(0.5 * s) / (u_lb * u_lb * n_unit * n_unit)
 
 
-def run(n_unit, t_end=1.0, dt_sample=0.002, storage="fp64", order=4, log=None):
+def run(n_unit, t_end=1.0, dt_sample=0.002, storage="fp64", order=4, log=None, u_lb=None):
     """Evolve the dipole to t_end; returns dict(times, enstrophy, energy, peaks, errors, ...).
 
+    u_lb: lattice velocity unit (default 0.01 * 125 / N, the constant-viscosity series); a fixed
+    value gives the constant-Mach series (U_lb = 0.032: the Ma 0.7 runs of Sec. 4.1).
     log: optional callable, given a progress line every 100 samples."""
     import workloads as W
 
     torch = _torch()
-    u_lb, nu, tau = lattice_parameters(n_unit)
+    u_lb, nu, tau = lattice_parameters(n_unit, u_lb)
     u_phys, _ = W.dipole(n_unit)
     m = 2 * n_unit + 1
     sim = Simulation("D2Q9", (1, m, m), tau, order, storage=storage)
@@ -88,6 +93,7 @@ def run(n_unit, t_end=1.0, dt_sample=0.002, storage="fp64", order=4, log=None):
     every = max(1, int(round(dt_sample * steps_per_unit)))
     total = int(round(t_end * steps_per_unit))
     times, ens, ke = [], [], []
+    umax = 0.0
     t0 = time.perf_counter()
     k = 0
     while True:
@@ -95,6 +101,7 @@ def run(n_unit, t_end=1.0, dt_sample=0.002, storage="fp64", order=4, log=None):
         times.append(k / steps_per_unit)
         ens.append(enstrophy_integral(v, n_unit, u_lb))
         ke.append(kinetic_energy(v, u_lb))
+        umax = max(umax, float(torch.sqrt(v[0] ** 2 + v[1] ** 2).max()))
         if log is not None and len(times) % 100 == 0:
             log(f"dipole N={n_unit} {storage}: t = {times[-1]:.3f}, enstrophy {ens[-1]:.1f}")
         if not np.isfinite(ens[-1]):
@@ -116,5 +123,6 @@ def run(n_unit, t_end=1.0, dt_sample=0.002, storage="fp64", order=4, log=None):
             peaks.append((float(times[i]), float(ens[i])))
     errors = [abs(p[1] - r) / r for p, r in zip(peaks, REFERENCE_PEAKS)]
     return {"n_unit": n_unit, "nodes": m * m, "u_lb": u_lb, "tau": tau, "steps": k, "storage": storage,
+            "umax": umax,
             "times": times, "enstrophy": ens, "energy": np.array(ke), "peaks": peaks, "errors": errors,
             "wall_s": wall, "glups": m * m * k / wall / 1e9}

@@ -7,7 +7,12 @@
 * the two enstrophy peaks at N = 250 against the reference values quoted in Sec. 4.1
   (3313 and 1418): first peak within 15%, second within 2%, at t = 0.30-0.36 and 0.57-0.65;
   the error of the first peak falls from N = 125 to N = 250 (measured on MI355X: N = 125
-  34% / 14%, N = 250 12.7% / 0.2%, N = 500 2.2% / 0.07%).
+  34% / 14%, N = 250 12.7% / 0.2%, N = 500 2.2% / 0.07%);
+* the constant-Mach series of Sec. 4.1 (U_lb = 0.032 at every N, the viscosity set by Re): the
+  order-4 model runs through t = 1 at a peak local Mach number above 0.7, its peak errors fall
+  from N = 125 to 500 and then level off (the compressibility error does not fall with N at
+  fixed Ma; measured 34% / 21%, 14% / 7.3%, 5.5% / 5.6%, 4.5% / 6.0% at N = 125 ... 1000),
+  while the order-2 regularised model loses its finite state before t = 0.5.
 """
 import numpy as np
 import pytest
@@ -61,3 +66,23 @@ def test_enstrophy_peaks_against_the_reference(lbrr, gpu):
     assert 0.30 <= t1 <= 0.36 and 0.57 <= t2 <= 0.65
     assert r["errors"][0] < 0.15 and r["errors"][1] < 0.02
     assert r["errors"][0] < res[125]["errors"][0]
+
+
+def test_constant_mach_07_series(lbrr, gpu):
+    from paper_1505_06900_amd import dipole as D
+
+    errs = {}
+    for n_unit in (125, 250, 500):
+        r = D.run(n_unit, storage="fp64", u_lb=0.032)
+        mach = r["umax"] / np.sqrt(1.0 / 3.0)
+        print(f"dipole Ma 0.7 N={n_unit} tau={r['tau']:.5f}: peak local Ma {mach:.3f} peaks "
+              f"{[(round(t, 3), round(v, 1)) for t, v in r['peaks']]} errors {[round(e, 4) for e in r['errors']]}",
+              flush=True)
+        assert np.all(np.isfinite(r["enstrophy"])) and r["steps"] == int(round(n_unit / 0.032))
+        assert mach > 0.7
+        errs[n_unit] = r["errors"]
+    assert errs[500][0] < errs[250][0] < errs[125][0] and errs[500][1] < errs[250][1] < errs[125][1]
+    assert max(errs[500]) < 0.08
+    r = D.run(125, t_end=0.5, storage="fp64", order=2, u_lb=0.032)
+    print(f"dipole Ma 0.7 N=125 order 2: finite until step {r['steps']} of {int(round(0.5 * 125 / 0.032))}", flush=True)
+    assert not np.all(np.isfinite(r["enstrophy"]))
