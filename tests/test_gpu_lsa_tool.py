@@ -1,0 +1,81 @@
+"""The stability-analysis tool on the GPU: Lambda measured from the library's own step (MI355X).
+
+* Lambda of every lattice and order, at rest and at two velocities, against the oracle's
+  complex-step Lambda (exact to rounding): absolute error <= 1e-9;
+* the paper's statements (Sec. 3.6, D2Q9, tau = 0.5001) through the tool: order 4 stable at
+  u = (0.2, 0) over the whole k-grid, unstable at 0.248; order 2 unstable along k_y = 0 at 0.2;
+* the onset speed the tool finds on a 32^2 grid brackets the oracle's: stable 2e-4 below it,
+  unstable 2e-4 above it;
+* D3Q19 order 4 grows at rest at tau = 0.51 (0.0285 per step on a 16^3 grid, as the oracle finds);
+* the command line writes its arrays and summary.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import test_gpu_parity as TP
+from oracle import lsa as OLSA
+
+pytestmark = pytest.mark.gpu
+
+VELOCITIES = {2: [(0.0, 0.0), (0.12, -0.07), (0.3, 0.1)], 3: [(0.0, 0.0, 0.0), (0.12, -0.07, 0.05), (0.25, 0.1, -0.1)]}
+
+
+@pytest.mark.parametrize("lat,N", TP.CASES)
+def test_jacobian_matches_the_oracle(lbrr, gpu, lat, N):
+    from paper_1505_06900_amd import lsa
+
+    D = 2 if lat == "D2Q9" else 3
+    tau = 0.6
+    vel = np.array(VELOCITIES[D])
+    J = lsa.jacobians(lat, N, tau, vel)
+    err = 0.0
+    for b, u in enumerate(vel):
+        ref = OLSA.jacobian(lat, N, tau, 1.0, u)
+        err = max(err, float(np.abs(J[b] - ref).max()))
+    print(f"lsa jacobian {lat} N={N}: max abs error vs oracle {err:.2e}", flush=True)
+    assert err <= 1e-9
+
+
+def test_paper_statements_through_the_tool(lbrr, gpu):
+    from paper_1505_06900_amd import lsa
+
+    g = lsa.max_growth("D2Q9", 4, 0.5001, [[0.2, 0.0], [0.248, 0.0]], nk=64)
+    _, w = lsa.dispersion_kx("D2Q9", 2, 0.5001, [0.2, 0.0], nk=401)
+    print(f"lsa D2Q9 tau=0.5001: max growth order 4 at u_x 0.2 {g[0]:.2e}, 0.248 {g[1]:.2e}; "
+          f"order 2 at 0.2 along k_y = 0 {w.imag.max():.2e}", flush=True)
+    assert g[0] < 1e-8 and g[1] > 1e-6
+    assert w.imag.max() > 1e-7
+
+
+def test_onset_speed_brackets_the_oracle(lbrr, gpu):
+    from paper_1505_06900_amd import lsa
+
+    s = lsa.stability_threshold("D2Q9", 4, 0.5001, (1.0, 0.0), nk=32, lo=0.15, hi=0.3, tol_u=5e-5)
+    print(f"lsa D2Q9 order 4 tau=0.5001 onset on 32^2: u_x = {s:.5f}", flush=True)
+    below = OLSA.max_growth("D2Q9", 4, 0.5001, 1.0, np.array([s - 2e-4, 0.0]), nk=32)
+    above = OLSA.max_growth("D2Q9", 4, 0.5001, 1.0, np.array([s + 2e-4, 0.0]), nk=32)
+    assert below < 1e-8 < above
+
+
+def test_d3q19_order4_rest_growth(lbrr, gpu):
+    from paper_1505_06900_amd import lsa
+
+    g = lsa.max_growth("D3Q19", 4, 0.51, [[0.0, 0.0, 0.0]], nk=16)[0]
+    g3 = lsa.max_growth("D3Q27", 4, 0.51, [[0.0, 0.0, 0.0]], nk=16)[0]
+    print(f"lsa rest growth tau=0.51: D3Q19 order 4 {g:.4f}, D3Q27 order 4 {g3:.2e}", flush=True)
+    assert g == pytest.approx(0.0285, abs=2e-3) and g3 < 1e-8
+
+
+def test_command_line(lbrr, gpu, tmp_path, capsys):
+    from paper_1505_06900_amd import lsa
+
+    out = tmp_path / "map.npz"
+    lsa.main(["map", "--lattice", "D2Q9", "--order", "4", "--tau", "0.5001", "--u", "0.248", "0", "--nk", "32",
+              "--out", str(out)])
+    summary = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    data = np.load(out)
+    assert data["max_im_omega"].shape == (32, 32)
+    assert summary["max_im_omega"] == pytest.approx(float(data["max_im_omega"].max()))
+    assert summary["unstable_fraction"] > 0
