@@ -73,7 +73,7 @@ def random_solenoidal3d(n, kmax, urms, seed, kmin=1.0, shape=None):
     kvec = np.stack([KX, KY, KZ])
     safe = np.where(k2 > 0, k2, 1.0)
     g = g - kvec * (np.sum(kvec * g, axis=0) / safe)  # project out the longitudinal part
-    u = np.stack([np.fft.irfftn(g[d], s=(nz, ny, nx)) for d in range(3)])
+    u = np.stack([np.fft.irfftn(g[d], s=(nz, ny, nx), axes=(0, 1, 2)) for d in range(3)])
     u *= urms / math.sqrt(np.mean(np.sum(u**2, axis=0)))
     return np.ones((nz, ny, nx)), u
 
