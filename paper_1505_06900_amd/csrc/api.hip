@@ -50,8 +50,9 @@ size_t elem_size(int storage) {
   return 2;
 }
 
-// z-planes per block of the moment-state step: each block rebuilds lz + 2
-// planes.  Short chunks measured faster on MI355X despite the extra rebuilds,
+// z-planes per block of the 3D moment-state step (rows of the 2D one): each
+// block rebuilds lz + 2 planes (rows).  2D: 4 rows (the measured optimum, see
+// kRowX).  3D:  Short chunks measured faster on MI355X despite the extra rebuilds,
 // down to the point where the lz + 2 planes a chunk reads outgrow the
 // aggregate L2 (8 x 4 MiB).  Measured, D3Q27 FP32 (GLUPS at lz = 2 / 3 / 4):
 // 256^2 planes 30 / 34 / 36, 320^2 30 / 33 / 33, 256 x 512 30 / 32 / 24,
@@ -65,6 +66,7 @@ int moment_lz(int64_t nx, int64_t ny, int nvalues, size_t es) {
     const int v = std::atoi(e);
     if (v >= 1) return v;
   }
+  if (nvalues == 6) return 4;  // 2D: rows per block of the y-marching step
   int lz = 4;
   if (es == 4)
     while (lz > 2 && double(lz + 2) * double(nx * ny) * nvalues * es > 27e6) --lz;

@@ -16,16 +16,17 @@
 // 3D fields: drho, jx, jy, jz, axx, ayy, azz, axy, axz, ayz; 2D: drho, jx,
 // jy, axx, ayy, axy.  FP64 or FP32; the collision runs in the same precision.
 //
-// Step kernel: a block rebuilds the populations of a kMX x TY patch of nodes
-// of one z-plane, exchanges them through LDS, and the inner (kMX-2) x (TY-2)
-// nodes pull theirs.  In 3D the block marches along z through a chunk of
+// Step kernel (3D): a block rebuilds the populations of a kMX x TY patch of
+// nodes of one z-plane, exchanges them through LDS, and the inner (kMX-2) x
+// (TY-2) nodes pull theirs.  The block marches along z through a chunk of
 // planes: the populations rebuilt on plane p with c_z = -1, 0, +1 arrive on
 // planes p-1, p, p+1, so each inner thread keeps running moment sums for
 // three target planes, and plane p-1 is complete once plane p has been
 // rebuilt.  A chunk of lz target planes rebuilds lz + 2 planes; a patch
 // rebuilds its one-node halo ring as well.  The halo and chunk overlaps are
 // the price of the 2.7x smaller state: the kernel is bound by the rebuild
-// arithmetic, not by HBM.
+// arithmetic, not by HBM.  The 2D step (k_mstep2) does the same one
+// dimension lower: a row of kRowX nodes marching along y.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,6 +42,12 @@ constexpr int kNM = (L::D == 3) ? 10 : 6;
 
 constexpr int kMX = 32;  // patch of rebuilt nodes per block: kMX x TY
 constexpr int kPrefetch = 2;  // planes of moments in flight ahead of the rebuild
+// 2D: nodes per rebuilt row of a block.  Measured, D2Q9 order 4 FP32, GLUPS at
+// 2 / 4 / 8 / 16 rows per chunk: 2048^2 rows of 128: 81 / 86 / 82 / 79, of 256:
+// 86 / 93 / 89 / 81, of 512: 76 / 81 / 85 / 76; 4096^2 rows of 256: 93 / 100 /
+// 94 / 85, of 512: 92 / 102 / 98 / 90 (population storage: 84 and 87).  The
+// host picks 4 rows per chunk.
+constexpr int kRowX = 256;
 
 // Hydrodynamic state of a node from its stored moments m.
 template <class L, class R>
@@ -165,6 +172,33 @@ __device__ __forceinline__ void add_layer(Moments<R>& s, const R (*pop)[TY][kMX]
   }
 }
 
+// 2D: add the populations with c_y = CY rebuilt on one row that arrive at
+// inner node tx to its moment sums s: population (cx, CY) comes from row node
+// tx - cx.
+template <class L, int CY, int BX, class R>
+__device__ __forceinline__ void add_row(Moments<R>& s, const R (*pop)[BX], int tx) {
+  R v[3];
+  sfor<0, 3>([&](auto X) {
+    constexpr int cx = int(X) - 1;
+    v[X] = pop[velocity_index<L>(cx, CY, 0)][tx - cx];
+  });
+  const R e = v[2] + v[0];
+  const R s0 = e + v[1], s1 = v[2] - v[0];
+  s.d0 = s.d0 + s0;
+  s.jx = s.jx + s1;
+  s.pxx = s.pxx + e;
+  if constexpr (CY != 0) {
+    s.pyy = s.pyy + s0;
+    if constexpr (CY > 0) {
+      s.jy = s.jy + s0;
+      s.pxy = s.pxy + s1;
+    } else {
+      s.jy = s.jy - s0;
+      s.pxy = s.pxy - s1;
+    }
+  }
+}
+
 // Block barrier for the LDS exchange: waits for the LDS accesses of every
 // wave but leaves global loads and stores in flight (threads of a block share
 // nothing through global memory here), so a prefetch survives the barrier.
@@ -182,6 +216,7 @@ __device__ __forceinline__ int wrap(int v, int n) {
 // One step of the moment-state update (see the file comment).
 template <class L, int N, class S, int TY>
 __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
+  static_assert(L::D == 3, "3D lattices; 2D runs k_mstep2");
   using R = S;
   constexpr int NM = kNM<L>;
   __shared__ R pop[L::Q][TY][kMX];
@@ -211,20 +246,7 @@ __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S
     sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], d + int64_t(C) * a.si); });
   };
 
-  if constexpr (L::D == 2) {
-    R m[NM];
-    load(0, m);
-    rebuild(m);
-    lds_barrier();
-    if (inner) {
-      Moments<R> acc;
-      clear(acc);
-      add_layer<L, 0, TY, R>(acc, pop, tx, ty);
-      R m2[NM];
-      finalize_state<L, R>(acc, rho0, m2);
-      put(0, m2);
-    }
-  } else {
+  {
     // The moments of a completed target plane are kept in registers and
     // stored at the start of the next iteration, next to the prefetch of the
     // plane kPrefetch ahead: loads and stores then have one or more whole
@@ -269,6 +291,78 @@ __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S
     }
     if (inner) put(z1 - 1, out);
   }
+}
+
+// One step of the 2D moment-state update.  A block of BX threads rebuilds a
+// row of BX nodes (x0 - 1 ... x0 + BX - 2) and marches along y through a
+// chunk of a.lz target rows: the populations rebuilt on row p with c_y = -1,
+// 0, +1 arrive on rows p - 1, p, p + 1, so each inner thread keeps running
+// moment sums for three target rows, and row p - 1 is complete once row p has
+// been rebuilt.  Rows of BX nodes keep the loads and stores of a field nearly
+// line-aligned (one partial 128-byte line per row and field), and the two-stage
+// prefetch ring of the 3D step overlaps them with the rebuilds.
+template <class L, int N, class S, int BX>
+__global__ void __launch_bounds__(BX) k_mstep2(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
+  using R = S;
+  constexpr int NM = kNM<L>;
+  static_assert(L::D == 2, "2D lattices only");
+  __shared__ R pop[L::Q][BX];
+  const int tx = threadIdx.x;
+  const int x0 = blockIdx.x * (BX - 2);
+  const int px = wrap(x0 - 1 + tx, a.nx);
+  const bool inner = tx >= 1 && tx <= BX - 2 && x0 + tx - 1 < a.nx;
+  const int xo = x0 + tx - 1;
+  const R rho0 = R(a.rho0), om = R(a.omega1);
+  auto load = [&](int y, R (&m)[NM]) {
+    const S* s = src + int64_t(y) * a.sy + px;
+    sfor<0, NM>([&](auto C) { m[C] = s[int64_t(C) * a.si]; });
+  };
+  auto put = [&](int y, const R (&m)[NM]) {
+    S* d = dst + int64_t(y) * a.sy + xo;
+    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], d + int64_t(C) * a.si); });
+  };
+  const int y0 = blockIdx.y * a.lz;
+  const int y1 = (y0 + a.lz < a.ny) ? y0 + a.lz : a.ny;
+  Moments<R> prev, cur, next;  // sums of target rows p-1, p, p+1
+  clear(prev);
+  clear(cur);
+  clear(next);
+  R pre[kPrefetch][NM];
+  sfor<0, kPrefetch>([&](auto K) {
+    if (y0 - 1 + int(K) <= y1) load(wrap(y0 - 1 + int(K), a.ny), pre[K]);
+  });
+  R out[NM];  // moments of target row py - 2, stored during iteration py
+  auto iteration = [&](int py, R (&buf)[NM]) __attribute__((always_inline)) {
+    R m[NM];
+    sfor<0, NM>([&](auto C) { m[C] = buf[C]; });
+    if (py + kPrefetch <= y1) load(wrap(py + kPrefetch, a.ny), buf);
+    if (inner && py >= y0 + 2) put(py - 2, out);
+    {
+      const Hydro<R> h = state_hydro<L, R>(m, rho0);
+      R C[3][3][3];
+      coefficients<L, N, R>(h, om, C);
+      R f[L::Q];
+      reconstruct<L, N, R>(C, f);
+      sfor<0, L::Q>([&](auto I) { pop[I][tx] = f[I]; });
+    }
+    lds_barrier();
+    if (inner) {
+      add_row<L, -1, BX, R>(prev, pop, tx);
+      add_row<L, 0, BX, R>(cur, pop, tx);
+      add_row<L, 1, BX, R>(next, pop, tx);
+      if (py >= y0 + 1) finalize_state<L, R>(prev, rho0, out);  // target row py - 1 is complete
+      prev = cur;
+      cur = next;
+      clear(next);
+    }
+    lds_barrier();
+  };
+  for (int py = y0 - 1; py <= y1; py += kPrefetch) {
+    sfor<0, kPrefetch>([&](auto K) {
+      if (py + int(K) <= y1) iteration(py + int(K), pre[K]);
+    });
+  }
+  if (inner) put(y1 - 1, out);
 }
 
 // Moment state at t = 0 from (rho, u[, pi1]): the pre-collision moments of
@@ -391,14 +485,22 @@ __global__ void __launch_bounds__(256) k_mpopulations(const S* __restrict__ src,
 // the z-planes off multiples of 64 KiB changed nothing.
 template <class L, int N, class S>
 hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream_t s) {
-  constexpr int TY = sizeof(S) == 4 ? 16 : 8;
-  if (L::D == 3 && a.lz < 1) return hipErrorInvalidValue;
-  dim3 grid(unsigned((a.nx + kMX - 3) / (kMX - 2)), unsigned((a.ny + TY - 3) / (TY - 2)),
-            unsigned(L::D == 3 ? (a.nz + a.lz - 1) / a.lz : 1));
-  if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_mstep<L, N, S, TY>), grid, dim3(kMX * TY), 0, s, static_cast<const S*>(src),
-                     static_cast<S*>(dst), a);
-  return hipGetLastError();
+  if (a.lz < 1) return hipErrorInvalidValue;
+  if constexpr (L::D == 2) {
+    dim3 grid2(unsigned((a.nx + kRowX - 3) / (kRowX - 2)), unsigned((a.ny + a.lz - 1) / a.lz));
+    if (grid2.y > 65535u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mstep2<L, N, S, kRowX>), grid2, dim3(kRowX), 0, s, static_cast<const S*>(src),
+                       static_cast<S*>(dst), a);
+    return hipGetLastError();
+  } else {
+    constexpr int TY = sizeof(S) == 4 ? 16 : 8;
+    dim3 grid(unsigned((a.nx + kMX - 3) / (kMX - 2)), unsigned((a.ny + TY - 3) / (TY - 2)),
+              unsigned((a.nz + a.lz - 1) / a.lz));
+    if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mstep<L, N, S, TY>), grid, dim3(kMX * TY), 0, s, static_cast<const S*>(src),
+                       static_cast<S*>(dst), a);
+    return hipGetLastError();
+  }
 }
 
 template <class L, int N, class S>

@@ -100,14 +100,15 @@ def test_moment_and_population_storage_agree(lbrr, gpu):
     assert abs(b[4] - a[4]) <= 1e-10 * a[4]
 
 
-def test_chunk_length_does_not_change_bits(lbrr, gpu, monkeypatch):
-    """Each node's moment sums are accumulated in the same order whatever the z-chunking."""
-    shape = (17, 9, 40)
-    rho, u, pi1 = TP.smooth_inputs(3, shape, 21)
+@pytest.mark.parametrize("lat,shape", [("D3Q27", (17, 9, 40)), ("D2Q9", (1, 17, 300))])
+def test_chunk_length_does_not_change_bits(lbrr, gpu, monkeypatch, lat, shape):
+    """Each node's moment sums are accumulated in the same order whatever the chunking (z-planes in
+    3D, rows in 2D)."""
+    rho, u, pi1 = TP.smooth_inputs(3 if shape[0] > 1 else 2, shape, 21)
     res = []
     for lz in ("1", "3", "17", "64"):
         monkeypatch.setenv("LBRR_MOM_LZ", lz)
-        sim = lbrr.Simulation("D3Q27", shape, 0.6, 4, storage="mom_fp32")
+        sim = lbrr.Simulation(lat, shape, 0.6, 4, storage="mom_fp32")
         sim.init_fields(rho, u, pi1)
         sim.step(5)
         res.append(sim.get_populations().cpu().numpy())
@@ -121,7 +122,9 @@ def test_small_boxes_and_block_edges(lbrr, gpu, monkeypatch, lat):
     L = OL.lattice(lat)
     monkeypatch.setenv("LBRR_MOM_LZ", "2")
     if L.D == 2:
-        shapes = [(1, 1, 1), (1, 2, 1), (1, 1, 3), (1, 6, 30), (1, 7, 31), (1, 12, 60), (1, 13, 61), (1, 5, 92)]
+        # rows of 254 inner nodes per block, chunks of 2 rows here
+        shapes = [(1, 1, 1), (1, 2, 1), (1, 1, 3), (1, 6, 30), (1, 7, 31), (1, 13, 61), (1, 3, 254), (1, 5, 255),
+                  (1, 4, 509), (1, 9, 600)]
     else:
         shapes = [(1, 1, 1), (1, 2, 3), (3, 1, 1), (2, 6, 30), (5, 7, 31), (3, 13, 61), (4, 5, 32)]
     for k, shape in enumerate(shapes):
