@@ -67,7 +67,10 @@ def measured_traffic(storage):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def run_gpu(P, torch, storage, rho, u, cfg, steps, warmup):
+def run_gpu(P, torch, storage, rho, u, cfg, steps, warmup, repeats=0, repeat_steps=200):
+    """Warm up, then time ``steps`` steps (wall clock and HIP events on the library's stream).
+    With repeats > 0, after the timed region: ``repeats`` more event-timed runs of
+    ``repeat_steps`` steps each, reported as kernel-time GLUPS (median, min, max)."""
     n = cfg["n"]
     sim = P.Simulation("D3Q27", (n, n, n), cfg["tau"], cfg["order"], storage=storage)
     sim.init_fields(rho, u)
@@ -89,10 +92,62 @@ def run_gpu(P, torch, storage, rho, u, cfg, steps, warmup):
         "kernel_ms": ev_ms / steps,
         "bytes_per_update": sim.bytes_per_update,
     }
-    _, vel = sim.moments()
+    _, vel = sim.moments()  # the state after warm-up + timed steps, compared across storages
     totals = sim.reduce()
+    if repeats > 0:
+        rates = []
+        for _ in range(repeats):
+            e0.record(stream)
+            sim.step(repeat_steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rates.append(nodes * repeat_steps / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+        rates.sort()
+        res["repeats"] = {"runs": repeats, "steps": repeat_steps, "median_glups": round(rates[len(rates) // 2], 3),
+                          "min_glups": round(rates[0], 3), "max_glups": round(rates[-1], 3)}
     sim.close()
     return res, vel, totals
+
+
+def device_record(torch):
+    """The device and software the numbers were taken on: GPU, ROCm / HIP / torch versions,
+    current clocks and power limits as rocm-smi reports them (None where unavailable)."""
+    import subprocess
+
+    props = torch.cuda.get_device_properties(0)
+    rec = {"name": props.name, "arch": getattr(props, "gcnArchName", None), "compute_units": props.multi_processor_count,
+           "hbm_gib": round(props.total_memory / 2**30, 1), "hip_runtime": torch.version.hip, "torch": torch.__version__}
+    try:
+        with open("/opt/rocm/.info/version") as fh:
+            rec["rocm"] = fh.read().strip()
+    except OSError:
+        rec["rocm"] = None
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showmaxpower", "--showpower", "--json"],
+                           capture_output=True, text=True, timeout=30)
+        card = next(iter(json.loads(r.stdout).values())) if r.returncode == 0 else {}
+        rec["smi"] = {k: v for k, v in card.items() if "clock" in k.lower() or "power" in k.lower()
+                      or k.lower().startswith(("sclk", "mclk", "fclk"))}
+    except (OSError, ValueError, StopIteration, subprocess.TimeoutExpired):
+        rec["smi"] = None
+    return rec
+
+
+def kernel_resources(B, storage):
+    """Registers, scratch, LDS and occupancy of the D3Q27 order-4 step kernel of ``storage``, as the
+    compiler reported them when the library was built."""
+    name = {"fp32": "k_step<lbrr::D3Q27, 4, float>", "fp16": "k_stepINS_5D3Q27ELi4EDF16_",
+            "fp64": "k_step<lbrr::D3Q27, 4, double>", "mom_fp32": "k_mstep<lbrr::D3Q27, 4, float, 16>",
+            "mom_fp64": "k_mstep<lbrr::D3Q27, 4, double, 8>"}[storage]
+    try:
+        with open(B.RESOURCES) as fh:
+            res = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    for k, v in res.items():
+        if name in k:
+            return {"kernel": k, **v}
+    return None
 
 
 def copy_probe(P, torch, nbytes=2 << 30, reps=10):
@@ -306,8 +361,9 @@ def main(argv=None):
         print(json.dumps(write_traffic(*a.write_traffic, TRAFFIC_FILE), indent=1))
         return 0
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the domain-decomposition design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the step would shard by z-slabs with a halo exchange per step, not implemented); use --gpus 1",
+              file=sys.stderr)
         return 2
 
     import numpy as np
@@ -334,7 +390,8 @@ def main(argv=None):
     results, vels = {}, {}
     for st in storages:
         log(f"running {st}: warmup {a.warmup}, timed {a.steps}")
-        res, vel, totals = run_gpu(P, torch, st, rho_t, u_t, cfg, a.steps, a.warmup)
+        res, vel, totals = run_gpu(P, torch, st, rho_t, u_t, cfg, a.steps, a.warmup,
+                                   repeats=5 if st == storages[0] else 0)
         results[st], vels[st] = res, vel
         log(f"{st}: {res['glups']:.2f} GLUPS, kernel {res['kernel_ms']:.3f} ms, totals {totals[0]:.6e}")
     errs = {}
@@ -373,6 +430,9 @@ def main(argv=None):
                                                  / (HBM_PEAK_GBS / 1000), 4),
                                "bytes_per_update": v["bytes_per_update"]} for st, v in results.items()},
         "l2_err_u_vs_fp64": {"steps": a.warmup + a.steps, **{k: float(f"{v:.3e}") for k, v in errs.items()}},
+        "repeats": r.get("repeats"),
+        "kernel_resources": kernel_resources(B, main_st),
+        "device": device_record(torch),
     }
     out["copy_probe"] = copy_probe(P, torch)
     log(f"copy probe: {out['copy_probe']['gbs']} GB/s")

@@ -6,6 +6,7 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import json
 import os
 import shutil
 import subprocess
@@ -16,6 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liblbrr.so")
+# per-kernel register, scratch, LDS and occupancy figures reported by the compiler
+RESOURCES = os.path.join(PKG, "liblbrr_resources.json")
 
 SOURCES = ["api.hip", "diag.hip", "closure.hip", "kernels_d2q9.hip", "kernels_d3q19.hip", "kernels_d3q27.hip"]
 
@@ -29,7 +32,34 @@ FLAGS = [
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # per-kernel resource usage as compiler remarks (analysis only; collected into RESOURCES)
+    "-Rpass-analysis=kernel-resource-usage",
 ]
+
+
+def parse_resource_remarks(text):
+    """{kernel name: {field: value}} from the compiler's kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        if "remark:" not in line or "kernel-resource-usage" not in line:
+            continue
+        body = line.split("remark:", 1)[1].rsplit("[-Rpass-analysis", 1)[0].strip()
+        key, _, val = body.partition(":")
+        key, val = key.strip(), val.strip()
+        if key == "Function Name":
+            cur = out.setdefault(val, {})
+        elif cur is not None and val:
+            cur[key] = int(val) if val.lstrip("-").isdigit() else val
+    return out
+
+
+def demangle(names):
+    exe = shutil.which("c++filt") or shutil.which("llvm-cxxfilt")
+    if not exe or not names:
+        return {n: n for n in names}
+    r = subprocess.run([exe], input="\n".join(names), capture_output=True, text=True)
+    out = r.stdout.splitlines() if r.returncode == 0 else []
+    return dict(zip(names, out)) if len(out) == len(names) else {n: n for n in names}
 
 
 def hipcc():
@@ -65,6 +95,12 @@ def build(jobs=None, verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    res = {}
+    for _, err in results:
+        res.update(parse_resource_remarks(err))
+    names = demangle(sorted(res))
+    with open(RESOURCES, "w") as fh:
+        json.dump({names[k]: v for k, v in sorted(res.items())}, fh, indent=1)
     return LIB
 
 
