@@ -64,7 +64,7 @@ enum lb_dtype { LB_F64 = 0, LB_F32 = 1 };
 enum lb_status {
   LB_OK = 0,
   LB_ERR_INVALID_ARG = -1, /* argument out of range, NULL pointer, wrong dims */
-  LB_ERR_UNSUPPORTED = -2, /* valid combination this build does not provide */
+  LB_ERR_UNSUPPORTED = -2, /* valid combination the library does not provide */
   LB_ERR_OOM = -3,         /* device allocation failed */
   LB_ERR_HIP = -4,         /* a HIP runtime call failed (message has the HIP error) */
   LB_ERR_UNSTABLE = -5,    /* non-finite density or velocity found by a check */
