@@ -52,14 +52,15 @@ size_t elem_size(int storage) {
 
 // z-planes per block of the 3D moment-state step (rows of the 2D one): each
 // block rebuilds lz + 2 planes (rows).  2D: 4 rows (the measured optimum, see
-// kRowX).  3D:  Short chunks measured faster on MI355X despite the extra rebuilds,
-// down to the point where the lz + 2 planes a chunk reads outgrow the
-// aggregate L2 (8 x 4 MiB).  Measured, D3Q27 FP32 (GLUPS at lz = 2 / 3 / 4):
-// 256^2 planes 30 / 34 / 36, 320^2 30 / 33 / 33, 256 x 512 30 / 32 / 24,
-// 384^2 30 / 28 / 25, 512^2 30 / 22 / 21, that is fast while the chunk reads
-// at most about 26 MB; so FP32 takes the largest lz <= 4 that stays within
-// 27 MB, and never less than 2.  FP64 (twice the bytes, half the arithmetic
-// rate) measured best at 4 at 256^3 and 384^3 (19-20 GLUPS, 16.5 at 2).
+// kRowX).  3D: short chunks measured faster on MI355X despite the extra
+// rebuilds, down to the point where the lz + 2 planes a chunk reads outgrow
+// the aggregate L2 (8 x 4 MiB).  Measured, D3Q27 FP32 (GLUPS at lz = 2 / 3 / 4
+// / 5 / 6 / 8): 256^2 planes 30.9 / 34.9 / 36.5 / 29.1 / 26.4 / 25.7, 384^2
+// 29.4 / 33.1 / 26.8 / 25.5 / 24.3 / 23.6, 512^2 29.0 / 26.5 / 21.9 / 21.6 /
+// 21.3 / 21.2: fast while a chunk reads at most about 30 MB (384^2 at lz 3:
+// 29.5 MB), slow from 35 MB on; so FP32 takes the largest lz <= 4 within
+// 30 MB, and never less than 2.  FP64 (twice the bytes, half the arithmetic
+// rate) measured best at 4 at 256^3 and 384^3 (19-21 GLUPS, 16.5 at 2).
 // LBRR_MOM_LZ overrides the choice.
 int moment_lz(int64_t nx, int64_t ny, int nvalues, size_t es) {
   if (const char* e = std::getenv("LBRR_MOM_LZ")) {
@@ -69,7 +70,7 @@ int moment_lz(int64_t nx, int64_t ny, int nvalues, size_t es) {
   if (nvalues == 6) return 4;  // 2D: rows per block of the y-marching step
   int lz = 4;
   if (es == 4)
-    while (lz > 2 && double(lz + 2) * double(nx * ny) * nvalues * es > 27e6) --lz;
+    while (lz > 2 && double(lz + 2) * double(nx * ny) * nvalues * es > 30e6) --lz;
   return lz;
 }
 

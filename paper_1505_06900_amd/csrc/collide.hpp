@@ -252,23 +252,28 @@ __device__ __forceinline__ void coefficients(const Hydro<R>& h, R omega1, R (&C)
 // w = (1/6, 2/3, 1/6) and n_a = (1, 1/3, 2/9):
 //   g(0) = 2/3 C0 - C2,  g(+-1) = 1/6 C0 +- 1/2 C1 + 1/2 C2.
 // Plain (D3Q19, after the Gram solve): g(0) = C0 - C2/3, g(+-1) = C0 +- C1 + 2/3 C2.
+// Every multiply-add of the transform is an explicit fused multiply-add, so
+// the bits of each output do not depend on which other outputs the caller
+// uses (a contraction left to the compiler can change with that).
+__device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <bool Weighted, bool Has1, bool Has2, class R>
 __device__ __forceinline__ void axis3(R c0, R c1, R c2, R& gm, R& g0, R& gp) {
   if constexpr (Weighted) {
     R t = R(1.0 / 6.0) * c0;
-    if constexpr (Has2) t = t + R(0.5) * c2;
+    if constexpr (Has2) t = fused(R(0.5), c2, t);
     if constexpr (Has1) {
-      const R h = R(0.5) * c1;
-      gm = t - h;
-      gp = t + h;
+      gm = fused(R(-0.5), c1, t);
+      gp = fused(R(0.5), c1, t);
     } else {
       gm = t;
       gp = t;
     }
-    g0 = Has2 ? R(2.0 / 3.0) * c0 - c2 : R(2.0 / 3.0) * c0;
+    g0 = Has2 ? fused(R(2.0 / 3.0), c0, -c2) : R(2.0 / 3.0) * c0;
   } else {
     R t = c0;
-    if constexpr (Has2) t = t + R(2.0 / 3.0) * c2;
+    if constexpr (Has2) t = fused(R(2.0 / 3.0), c2, c0);
     if constexpr (Has1) {
       gm = t - c1;
       gp = t + c1;
@@ -276,7 +281,7 @@ __device__ __forceinline__ void axis3(R c0, R c1, R c2, R& gm, R& g0, R& gp) {
       gm = t;
       gp = t;
     }
-    g0 = Has2 ? c0 - R(1.0 / 3.0) * c2 : c0;
+    g0 = Has2 ? fused(R(-1.0 / 3.0), c2, c0) : c0;
   }
 }
 
@@ -346,9 +351,12 @@ struct GramD3Q19Table {
   static constexpr GramD3Q19<N> t{};
 };
 
-// Post-collision deviations of the lattice's q populations from C.
-template <class L, int N, class R>
+// Post-collision deviations of the lattice's q populations from C.  With
+// ZSel = -1 or +1 (3D) only the populations with c_z = ZSel are written (the
+// other entries of out are left untouched); ZSel = 2 writes all q.
+template <class L, int N, class R, int ZSel = 2>
 __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
+  static_assert(ZSel == 2 || (L::D == 3 && (ZSel == -1 || ZSel == 1)), "layer selection is 3D only");
   constexpr bool W = L::kProduct;
   R B[3][3][3];
   if constexpr (W) {
@@ -366,7 +374,7 @@ __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
           constexpr int a2 = S / 9, b2 = (S / 3) % 3, c2 = S % 3;
           if constexpr (kept<L, N>(a2, b2, c2)) {
             constexpr double g = GramD3Q19Table<N>::t.inv[P][S];
-            if constexpr (g != 0.0) s = s + R(g) * C[a2][b2][c2];
+            if constexpr (g != 0.0) s = fused(R(g), C[a2][b2][c2], s);
           }
         });
         B[a][b][c] = s;
@@ -396,7 +404,7 @@ __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
   sfor<0, 3>([&](auto A) {
     sfor<0, NZ>([&](auto Z) {
       constexpr int a = A;
-      if constexpr (kept<L, N>(a, 0, 0)) {
+      if constexpr (kept<L, N>(a, 0, 0) && (ZSel == 2 || int(Z) == ZSel + 1)) {
         constexpr bool h1 = kept<L, N>(a, 1, 0), h2 = kept<L, N>(a, 2, 0);
         axis3<W, h1, h2>(G1[a][0][Z], h1 ? G1[a][1][Z] : R(0), h2 ? G1[a][2][Z] : R(0),
                          G2[a][0][Z], G2[a][1][Z], G2[a][2][Z]);
@@ -405,7 +413,7 @@ __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
   });
   // stage x: G2[*][cy][cz] -> populations; D3Q19 multiplies by w_i and skips corners
   sfor<0, NZ>([&](auto Z) {
-    sfor<0, 3>([&](auto Y) {
+    if constexpr (ZSel == 2 || int(Z) == ZSel + 1) sfor<0, 3>([&](auto Y) {
       R gm, g0, gp;
       axis3<W, true, true>(G2[0][Y][Z], G2[1][Y][Z], G2[2][Y][Z], gm, g0, gp);
       sfor<0, L::Q>([&](auto I) {

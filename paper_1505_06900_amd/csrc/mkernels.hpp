@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -233,13 +234,18 @@ __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S
     const S* s = src + int64_t(z) * a.sz + col_in;
     sfor<0, NM>([&](auto C) { m[C] = s[int64_t(C) * a.si]; });
   };
-  auto rebuild = [&](const R (&m)[NM]) {
+  // Rebuild the populations of this thread's patch node into LDS; ZS selects
+  // all of them (2) or only those with c_z = ZS (the planes next to a chunk).
+  auto rebuild = [&](const R (&m)[NM], auto ZS) __attribute__((always_inline)) {
+    constexpr int Z = decltype(ZS)::value;
     const Hydro<R> h = state_hydro<L, R>(m, rho0);
     R C[3][3][3];
     coefficients<L, N, R>(h, om, C);
     R f[L::Q];
-    reconstruct<L, N, R>(C, f);
-    sfor<0, L::Q>([&](auto I) { pop[I][ty][tx] = f[I]; });
+    reconstruct<L, N, R, Z>(C, f);
+    sfor<0, L::Q>([&](auto I) {
+      if constexpr (Z == 2 || L::cz(I) == Z) pop[I][ty][tx] = f[I];
+    });
   };
   auto put = [&](int z, const R (&m)[NM]) {
     S* d = dst + int64_t(z) * a.sz + col_out;
@@ -247,47 +253,70 @@ __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S
   };
 
   {
-    // The moments of a completed target plane are kept in registers and
-    // stored at the start of the next iteration, next to the prefetch of the
-    // plane kPrefetch ahead: loads and stores then have one or more whole
-    // rebuilds to complete before they are waited for.
+    // Target planes z0 .. z1-1; planes z0-1 .. z1 are rebuilt.  Plane z0-1
+    // reaches only target z0 (its c_z = +1 populations) and plane z1 only
+    // target z1-1 (c_z = -1), so those two rebuild a third of the populations
+    // and add one layer.  The moments of a completed target plane are kept in
+    // registers and stored at the start of the next iteration, next to the
+    // prefetch of the plane kPrefetch ahead: loads and stores then have one or
+    // more whole rebuilds to complete before they are waited for.
+    static_assert(kPrefetch == 2, "the buffer rotation below assumes two planes in flight");
     const int z0 = bz * a.lz;
     const int z1 = (z0 + a.lz < a.nz) ? z0 + a.lz : a.nz;
     Moments<R> prev, cur, next;  // sums of target planes p-1, p, p+1
     clear(prev);
     clear(cur);
     clear(next);
-    // Moments of the planes to rebuild, kPrefetch planes in flight: the loop
-    // is unrolled kPrefetch times so that buffer k always holds the planes
-    // pz = z0 - 1 + k (mod kPrefetch); a buffer is refilled with the plane
-    // kPrefetch further on as soon as its contents are taken.
+    // Moments of the planes to rebuild, two planes in flight: plane p sits in
+    // buffer (p - z0 + 1) mod 2, which is refilled with plane p + 2 as soon as
+    // its contents are taken.
     R pre[kPrefetch][NM];
-    sfor<0, kPrefetch>([&](auto K) {
-      if (z0 - 1 + int(K) <= z1) load(wrap(z0 - 1 + int(K), a.nz), pre[K]);
-    });
+    load(wrap(z0 - 1, a.nz), pre[0]);
+    load(wrap(z0, a.nz), pre[1]);
     R out[NM];  // moments of target plane pz - 2, stored during iteration pz
-    auto iteration = [&](int pz, R (&buf)[NM]) __attribute__((always_inline)) {
+    // E = 2: plane inside the chunk; +1: plane z0 - 1; -1: plane z1.
+    auto iteration = [&](int pz, R (&buf)[NM], auto ES) __attribute__((always_inline)) {
+      constexpr int E = decltype(ES)::value;
       R m[NM];
       sfor<0, NM>([&](auto C) { m[C] = buf[C]; });
       if (pz + kPrefetch <= z1) load(wrap(pz + kPrefetch, a.nz), buf);
       if (inner && pz >= z0 + 2) put(pz - 2, out);
-      rebuild(m);
+      rebuild(m, ES);
       lds_barrier();
       if (inner) {
-        add_layer<L, -1, TY, R>(prev, pop, tx, ty);
-        add_layer<L, 0, TY, R>(cur, pop, tx, ty);
-        add_layer<L, 1, TY, R>(next, pop, tx, ty);
-        if (pz >= z0 + 1) finalize_state<L, R>(prev, rho0, out);  // target plane pz - 1 is complete
-        prev = cur;
-        cur = next;
-        clear(next);
+        if constexpr (E == 1) {
+          add_layer<L, 1, TY, R>(next, pop, tx, ty);  // target z0
+          cur = next;
+          clear(next);
+        } else if constexpr (E == -1) {
+          add_layer<L, -1, TY, R>(prev, pop, tx, ty);  // target z1 - 1 is complete
+          finalize_state<L, R>(prev, rho0, out);
+        } else {
+          if (pz >= z0 + 1) add_layer<L, -1, TY, R>(prev, pop, tx, ty);
+          add_layer<L, 0, TY, R>(cur, pop, tx, ty);
+          if (pz + 1 < z1) add_layer<L, 1, TY, R>(next, pop, tx, ty);
+          if (pz >= z0 + 1) finalize_state<L, R>(prev, rho0, out);  // target plane pz - 1 is complete
+          prev = cur;
+          cur = next;
+          clear(next);
+        }
       }
       lds_barrier();
     };
-    for (int pz = z0 - 1; pz <= z1; pz += kPrefetch) {
-      sfor<0, kPrefetch>([&](auto K) {
-        if (pz + int(K) <= z1) iteration(pz + int(K), pre[K]);
-      });
+    using first_plane = std::integral_constant<int, 1>;
+    using inner_plane = std::integral_constant<int, 2>;
+    using last_plane = std::integral_constant<int, -1>;
+    iteration(z0 - 1, pre[0], first_plane{});
+    int pz = z0;
+    for (; pz + 1 < z1; pz += 2) {
+      iteration(pz, pre[1], inner_plane{});
+      iteration(pz + 1, pre[0], inner_plane{});
+    }
+    if (pz < z1) {  // one inner plane left: pz = z1 - 1, then z1 in buffer 0
+      iteration(pz, pre[1], inner_plane{});
+      iteration(z1, pre[0], last_plane{});
+    } else {  // pz = z1, in buffer 1
+      iteration(z1, pre[1], last_plane{});
     }
     if (inner) put(z1 - 1, out);
   }
