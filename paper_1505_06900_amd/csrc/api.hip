@@ -50,28 +50,40 @@ size_t elem_size(int storage) {
   return 2;
 }
 
-// z-planes per block of the 3D moment-state step (rows of the 2D one): each
-// block rebuilds lz + 2 planes (rows).  2D: 4 rows (the measured optimum, see
-// kRowX).  3D: short chunks measured faster on MI355X despite the extra
-// rebuilds, down to the point where the lz + 2 planes a chunk reads outgrow
-// the aggregate L2 (8 x 4 MiB).  Measured, D3Q27 FP32 (GLUPS at lz = 2 / 3 / 4
-// / 5 / 6 / 8): 256^2 planes 30.9 / 34.9 / 36.5 / 29.1 / 26.4 / 25.7, 384^2
-// 29.4 / 33.1 / 26.8 / 25.5 / 24.3 / 23.6, 512^2 29.0 / 26.5 / 21.9 / 21.6 /
-// 21.3 / 21.2: fast while a chunk reads at most about 30 MB (384^2 at lz 3:
-// 29.5 MB), slow from 35 MB on; so FP32 takes the largest lz <= 4 within
-// 30 MB, and never less than 2.  FP64 (twice the bytes, half the arithmetic
-// rate) measured best at 4 at 256^3 and 384^3 (19-21 GLUPS, 16.5 at 2).
-// LBRR_MOM_LZ overrides the choice.
-int moment_lz(int64_t nx, int64_t ny, int nvalues, size_t es) {
+// Block order and chunk length of the moment-state step.
+//   2D: rows per block = 4 (the measured optimum, see kRowX).
+//   3D: z-planes per block lz (each block rebuilds lz + 2 planes) and whether
+//   each XCD takes a contiguous range of tiles.  Measured, D3Q27 FP32, GLUPS at
+//   lz = 2 / 3 / 4, plain block order vs contiguous ranges per XCD:
+//     256^2 planes  31.0 / 35.1 / 36.6   vs 34.2 / 35.4 / 34.1
+//     320^2         29.0 / 33.4 / 34.5   vs 33.9 / 35.8 / 35.3
+//     384^2         28.8 / 33.3 / 28.5   vs 33.3 / 33.4 / 31.4
+//     448^2         29.5 / 25.9 / 23.9   vs 32.9 / 32.3 / 31.1
+//     512^2         28.5 / 32.3 / 23.4   vs 30.3 / 29.9 / 29.8
+//   In plain order the rate falls off a cliff once the lz + 2 planes of the
+//   chunks in flight outgrow the L2s; with contiguous ranges it stays within
+//   30-36 for every lz.  FP32 takes plain order and lz = 4 while those six
+//   planes fit in 16 MB (256^2 planes and smaller), else contiguous ranges and
+//   lz = 3.  FP64 (twice the bytes, half the arithmetic rate, less sensitive)
+//   keeps plain order and lz = 4 (19-21 GLUPS at 256^3 and 384^3).
+//   LBRR_MOM_LZ and LBRR_MOM_XCD override the choices.
+struct MomentSchedule {
+  int lz, xcd_tiles;
+};
+MomentSchedule moment_schedule(int64_t nx, int64_t ny, int nvalues, size_t es) {
+  MomentSchedule m{4, 0};
+  if (nvalues == 6) {
+    m.lz = 4;  // 2D rows per block
+  } else if (es == 4 && 6.0 * double(nx * ny) * nvalues * es > 16e6) {
+    m.lz = 3;
+    m.xcd_tiles = 1;
+  }
   if (const char* e = std::getenv("LBRR_MOM_LZ")) {
     const int v = std::atoi(e);
-    if (v >= 1) return v;
+    if (v >= 1) m.lz = v;
   }
-  if (nvalues == 6) return 4;  // 2D: rows per block of the y-marching step
-  int lz = 4;
-  if (es == 4)
-    while (lz > 2 && double(lz + 2) * double(nx * ny) * nvalues * es > 30e6) --lz;
-  return lz;
+  if (const char* e = std::getenv("LBRR_MOM_XCD")) m.xcd_tiles = std::atoi(e) != 0;
+  return m;
 }
 
 // Extra bytes after each population plane (layouts 0 and 2).  Planes whose
@@ -133,7 +145,13 @@ struct lb_ctx {
     a.sz = sz;
     a.rho0 = rho0;
     a.omega1 = 1.0 - 1.0 / tau;
-    a.lz = moment() ? moment_lz(nx, ny, nvalues(), elem_size(storage)) : 1;
+    if (moment()) {
+      const MomentSchedule m = moment_schedule(nx, ny, nvalues(), elem_size(storage));
+      a.lz = m.lz;
+      a.xcd_tiles = m.xcd_tiles;
+    } else {
+      a.lz = 1;
+    }
     return a;
   }
   void release() {

@@ -222,7 +222,19 @@ __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S
   constexpr int NM = kNM<L>;
   __shared__ R pop[L::Q][TY][kMX];
   const int tx = threadIdx.x % kMX, ty = threadIdx.x / kMX;
-  const int x0 = blockIdx.x * (kMX - 2), y0 = blockIdx.y * (TY - 2), bz = blockIdx.z;
+  const int gx = (a.nx + kMX - 3) / (kMX - 2), gy = (a.ny + TY - 3) / (TY - 2);
+  // Blocks are handed to the 8 XCDs round-robin by id.  With a.xcd_tiles the
+  // ids k, k + 8, k + 16, ... of XCD k take one contiguous range of tiles
+  // (x fastest, then y, then the z-chunk), so that neighbouring tiles share
+  // that XCD's L2; the first 8 * (nb / 8) ids are permuted, the rest kept.
+  const int nb = int(gridDim.x);
+  int t = int(blockIdx.x);
+  if (a.xcd_tiles) {
+    const int q = nb / 8;
+    if (t < 8 * q) t = (t % 8) * q + t / 8;
+  }
+  const int bxi = t % gx, byi = (t / gx) % gy, bz = t / (gx * gy);
+  const int x0 = bxi * (kMX - 2), y0 = byi * (TY - 2);
   // the patch node this thread rebuilds, and the node it updates if inner
   const int px = wrap(x0 - 1 + tx, a.nx), py = wrap(y0 - 1 + ty, a.ny);
   const bool inner = tx >= 1 && tx <= kMX - 2 && ty >= 1 && ty <= TY - 2 && x0 + tx - 1 < a.nx && y0 + ty - 1 < a.ny;
@@ -508,10 +520,11 @@ __global__ void __launch_bounds__(256) k_mpopulations(const S* __restrict__ src,
 // Measured on the 256^3 D3Q27 step (FP32, fields of a row together): 8, 16
 // and 32 rows within 6%; 4 z-planes per chunk best (36 GLUPS), 8 and more
 // 30% slower (larger planes want shorter chunks: the host's choice of lz);
-// handing XCDs blocks of neighbouring tiles lowered the L2-miss traffic by
-// half but not the time, and so did dispatching the z-chunks of a tile next
-// to each other (24-27 GLUPS at 256^3 and 512^3 for lz = 2 to 32); padding
-// the z-planes off multiples of 64 KiB changed nothing.
+// dispatching the z-chunks of a tile next to each other gave 24-27 GLUPS at
+// 256^3 and 512^3 for lz = 2 to 32; padding the z-planes off multiples of
+// 64 KiB changed nothing.  Contiguous tile ranges per XCD (a.xcd_tiles) make
+// the rate nearly independent of lz and of the plane size; the host turns
+// them on for large planes (host side, moment_schedule).
 template <class L, int N, class S>
 hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream_t s) {
   if (a.lz < 1) return hipErrorInvalidValue;
@@ -523,10 +536,10 @@ hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream
     return hipGetLastError();
   } else {
     constexpr int TY = sizeof(S) == 4 ? 16 : 8;
-    dim3 grid(unsigned((a.nx + kMX - 3) / (kMX - 2)), unsigned((a.ny + TY - 3) / (TY - 2)),
-              unsigned((a.nz + a.lz - 1) / a.lz));
-    if (grid.y > 65535u || grid.z > 65535u) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mstep<L, N, S, TY>), grid, dim3(kMX * TY), 0, s, static_cast<const S*>(src),
+    const int64_t nb = int64_t((a.nx + kMX - 3) / (kMX - 2)) * ((a.ny + TY - 3) / (TY - 2)) *
+                       ((a.nz + a.lz - 1) / a.lz);
+    if (nb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_mstep<L, N, S, TY>), dim3(unsigned(nb)), dim3(kMX * TY), 0, s, static_cast<const S*>(src),
                        static_cast<S*>(dst), a);
     return hipGetLastError();
   }

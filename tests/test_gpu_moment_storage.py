@@ -124,6 +124,24 @@ def test_chunk_length_changes_rounding_only(lbrr, gpu, monkeypatch, lat, shape):
             assert np.abs(r - res[0]).max() <= 1e-6 * np.abs(res[0]).max()
 
 
+@pytest.mark.parametrize("lat", ["D3Q27", "D3Q19"])
+def test_xcd_tile_order_changes_nothing(lbrr, gpu, monkeypatch, lat):
+    """Contiguous tile ranges per XCD only reorder the blocks: the state is bitwise the one of
+    the plain order, and matches the oracle.  45 blocks (3 x 3 tiles x 5 chunks of 3 planes):
+    40 permuted, 5 kept."""
+    shape = (13, 37, 70)
+    monkeypatch.setenv("LBRR_MOM_LZ", "3")
+    res = []
+    for order in ("0", "1"):
+        monkeypatch.setenv("LBRR_MOM_XCD", order)
+        res.append(TP.gpu_run(lbrr, lat, 4, 0.66, shape, 3, 77, "mom_fp32"))
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    ref = TP.oracle_run(lat, 4, 0.66, shape, 3, 77)
+    e = [max(TP.rel_l2(g, r), TP.rel_linf(g, r)) for g, r in zip(res[1][:2], ref[:2])]
+    assert e[0] <= 1e-5 and e[1] <= 1e-5
+
+
 @pytest.mark.parametrize("lat", ["D2Q9", "D3Q19", "D3Q27"])
 def test_small_boxes_and_block_edges(lbrr, gpu, monkeypatch, lat):
     L = OL.lattice(lat)
