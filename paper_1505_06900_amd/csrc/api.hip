@@ -210,25 +210,29 @@ int ensure_buffers(lb_ctx* h) {
   const size_t es = elem_size(h->storage);
   const int64_t nx = h->nx, ny = h->ny, nz = h->nz, q = h->nvalues();
   h->layout = h->moment() ? moment_layout_choice() : layout_choice(h->d(), nx, ny, es);
+  // Row pitch: nx rounded up to whole 128-byte lines, so that every row starts
+  // on a line and a wave's 64 consecutive x stay within the fewest lines (with
+  // nx = 300 unpadded, D3Q27 FP32 ran at 13.9 GLUPS against 27 for 256 or 320).
+  const int64_t px = int64_t((size_t(nx) * es + 127) / 128 * 128 / es);
   size_t elems = 0;
   if (h->layout == 1) {  // rows of all populations together
-    h->si = nx;
-    h->sy = q * nx;
-    h->sz = ny * q * nx;
-    elems = size_t(nz * ny * q * nx);
+    h->si = px;
+    h->sy = q * px;
+    h->sz = ny * q * px;
+    elems = size_t(nz * ny * q * px);
   } else {
-    const size_t plane = size_t(h->layout == 0 ? nx * ny * nz : nx * ny) * es;
+    const size_t plane = size_t(h->layout == 0 ? px * ny * nz : px * ny) * es;
     const size_t plane_al = (plane + 255) / 256 * 256;
     const size_t plane_bytes = plane_al + plane_pad_bytes(plane_al);
     const int64_t p = int64_t(plane_bytes / es);
     if (h->layout == 0) {
       h->si = p;
-      h->sy = nx;
-      h->sz = nx * ny;
+      h->sy = px;
+      h->sz = px * ny;
       elems = size_t(q * p);
     } else {
       h->si = p;
-      h->sy = nx;
+      h->sy = px;
       h->sz = q * p;
       elems = size_t(nz * q * p);
     }
