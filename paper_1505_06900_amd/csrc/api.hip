@@ -50,40 +50,23 @@ size_t elem_size(int storage) {
   return 2;
 }
 
-// Block order and chunk length of the moment-state step.
-//   2D: rows per block = 4 (the measured optimum, see kRowX).
-//   3D: z-planes per block lz (each block rebuilds lz + 2 planes) and whether
-//   each XCD takes a contiguous range of tiles.  Measured, D3Q27 FP32, GLUPS at
-//   lz = 2 / 3 / 4, plain block order vs contiguous ranges per XCD:
-//     256^2 planes  31.0 / 35.1 / 36.6   vs 34.2 / 35.4 / 34.1
-//     320^2         29.0 / 33.4 / 34.5   vs 33.9 / 35.8 / 35.3
-//     384^2         28.8 / 33.3 / 28.5   vs 33.3 / 33.4 / 31.4
-//     448^2         29.5 / 25.9 / 23.9   vs 32.9 / 32.3 / 31.1
-//     512^2         28.5 / 32.3 / 23.4   vs 30.3 / 29.9 / 29.8
-//   In plain order the rate falls off a cliff once the lz + 2 planes of the
-//   chunks in flight outgrow the L2s; with contiguous ranges it stays within
-//   30-36 for every lz.  FP32 takes plain order and lz = 4 while those six
-//   planes fit in 16 MB (256^2 planes and smaller), else contiguous ranges and
-//   lz = 3.  FP64 (twice the bytes, half the arithmetic rate, less sensitive)
-//   keeps plain order and lz = 4 (19-21 GLUPS at 256^3 and 384^3).
-//   LBRR_MOM_LZ and LBRR_MOM_XCD override the choices.
-struct MomentSchedule {
-  int lz, xcd_tiles;
-};
-MomentSchedule moment_schedule(int64_t nx, int64_t ny, int nvalues, size_t es) {
-  MomentSchedule m{4, 0};
-  if (nvalues == 6) {
-    m.lz = 4;  // 2D rows per block
-  } else if (es == 4 && 6.0 * double(nx * ny) * nvalues * es > 16e6) {
-    m.lz = 3;
-    m.xcd_tiles = 1;
-  }
+// Chunk length of the moment-state step: rows per block in 2D, z-planes per
+// block in 3D (each block rebuilds lz + 2).  Measured on MI355X:
+//   2D, rows of 256 nodes: 4 rows best (see kRowX).
+//   3D FP32, 64 x 8 patches, D3Q27 (GLUPS at lz = 4 / 6 / 8 / 12 / 16 / 32):
+//     256^3 36.1 / 37.1 / 37.4 / 38.1 / 37.2 / 33.7
+//     384^3 38.5 / 39.8 / 39.9 / 38.3 / 36.5 / 35.0
+//     512^3 39.5 / 40.8 / 41.0 / 37.4 / 36.5 / 35.3
+//   and D3Q19 order 3 ran 37-43 at 6 but 33-36 at 8: FP32 takes 6.
+//   3D FP64, 32 x 8 patches: 4 (19-21 GLUPS at 256^3 and 384^3, 16.5 at 2).
+// LBRR_MOM_LZ overrides the choice.
+int moment_lz(int nvalues, size_t es) {
   if (const char* e = std::getenv("LBRR_MOM_LZ")) {
     const int v = std::atoi(e);
-    if (v >= 1) m.lz = v;
+    if (v >= 1) return v;
   }
-  if (const char* e = std::getenv("LBRR_MOM_XCD")) m.xcd_tiles = std::atoi(e) != 0;
-  return m;
+  if (nvalues == 6) return 4;
+  return es == 4 ? 6 : 4;
 }
 
 // Extra bytes after each population plane (layouts 0 and 2).  Planes whose
@@ -145,13 +128,7 @@ struct lb_ctx {
     a.sz = sz;
     a.rho0 = rho0;
     a.omega1 = 1.0 - 1.0 / tau;
-    if (moment()) {
-      const MomentSchedule m = moment_schedule(nx, ny, nvalues(), elem_size(storage));
-      a.lz = m.lz;
-      a.xcd_tiles = m.xcd_tiles;
-    } else {
-      a.lz = 1;
-    }
+    a.lz = moment() ? moment_lz(nvalues(), elem_size(storage)) : 1;
     return a;
   }
   void release() {

@@ -16,9 +16,9 @@
 // 3D fields: drho, jx, jy, jz, axx, ayy, azz, axy, axz, ayz; 2D: drho, jx,
 // jy, axx, ayy, axy.  FP64 or FP32; the collision runs in the same precision.
 //
-// Step kernel (3D): a block rebuilds the populations of a kMX x TY patch of
-// nodes of one z-plane, exchanges them through LDS, and the inner (kMX-2) x
-// (TY-2) nodes pull theirs.  The block marches along z through a chunk of
+// Step kernel (3D): a block rebuilds the populations of an MX x TY patch of
+// nodes of one z-plane (64 x 8 in FP32, 32 x 8 in FP64: 55 KiB of LDS),
+// exchanges them through LDS, and the inner (MX-2) x (TY-2) nodes pull theirs.  The block marches along z through a chunk of
 // planes: the populations rebuilt on plane p with c_z = -1, 0, +1 arrive on
 // planes p-1, p, p+1, so each inner thread keeps running moment sums for
 // three target planes, and plane p-1 is complete once plane p has been
@@ -41,7 +41,19 @@ namespace lbrr {
 template <class L>
 constexpr int kNM = (L::D == 3) ? 10 : 6;
 
-constexpr int kMX = 32;  // patch of rebuilt nodes per block: kMX x TY
+// Patch of rebuilt nodes per block of the 3D step: MX x TY.  A row of the
+// patch is read as MX consecutive values of each field starting one node
+// before a tile, so it spans one 128-byte line more than it needs; 64 wide,
+// that is 3 lines for 62 outputs (FP32) instead of 2 for 30.  Measured,
+// D3Q27 FP32 (GLUPS, best chunk length): 32 x 16 patches 36.5 / 33.3 / 30.5
+// at 256^3 / 384^3 / 512^3 (the larger boxes only with contiguous tile
+// ranges per XCD, otherwise falling to 21-27 past a plane-size threshold),
+// 64 x 8 patches 37.1 / 39.8 / 40.8 at 6 planes per chunk in plain block
+// order, 64 x 16 (1024 threads) spills registers and ran 33.6-39.1.
+template <class S>
+struct MPatch {
+  static constexpr int MX = sizeof(S) == 4 ? 64 : 32, TY = 8;
+};
 constexpr int kPrefetch = 2;  // planes of moments in flight ahead of the rebuild
 // 2D: nodes per rebuilt row of a block.  Measured, D2Q9 order 4 FP32, GLUPS at
 // 2 / 4 / 8 / 16 rows per chunk: 2048^2 rows of 128: 81 / 86 / 82 / 79, of 256:
@@ -126,8 +138,8 @@ constexpr int velocity_index(int cx, int cy, int cz) {
 // Add the populations of the layer c_z = CZ that arrive at inner node (tx, ty)
 // to its moment sums s: population (cx, cy, CZ) comes from patch node
 // (tx - cx, ty - cy).  Sums along x, then y, then the c_z factors.
-template <class L, int CZ, int TY, class R>
-__device__ __forceinline__ void add_layer(Moments<R>& s, const R (*pop)[TY][kMX], int tx, int ty) {
+template <class L, int CZ, int TY, int MX, class R>
+__device__ __forceinline__ void add_layer(Moments<R>& s, const R (*pop)[TY][MX], int tx, int ty) {
   R r0[3], r1[3], r2[3];  // per row cy: sum of v, cx v, cx^2 v
   sfor<0, 3>([&](auto Y) {
     constexpr int cy = int(Y) - 1;
@@ -215,29 +227,21 @@ __device__ __forceinline__ int wrap(int v, int n) {
 }
 
 // One step of the moment-state update (see the file comment).
-template <class L, int N, class S, int TY>
-__global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
+template <class L, int N, class S, int TY, int MX>
+__global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
   static_assert(L::D == 3, "3D lattices; 2D runs k_mstep2");
   using R = S;
   constexpr int NM = kNM<L>;
-  __shared__ R pop[L::Q][TY][kMX];
-  const int tx = threadIdx.x % kMX, ty = threadIdx.x / kMX;
-  const int gx = (a.nx + kMX - 3) / (kMX - 2), gy = (a.ny + TY - 3) / (TY - 2);
-  // Blocks are handed to the 8 XCDs round-robin by id.  With a.xcd_tiles the
-  // ids k, k + 8, k + 16, ... of XCD k take one contiguous range of tiles
-  // (x fastest, then y, then the z-chunk), so that neighbouring tiles share
-  // that XCD's L2; the first 8 * (nb / 8) ids are permuted, the rest kept.
-  const int nb = int(gridDim.x);
-  int t = int(blockIdx.x);
-  if (a.xcd_tiles) {
-    const int q = nb / 8;
-    if (t < 8 * q) t = (t % 8) * q + t / 8;
-  }
+  __shared__ R pop[L::Q][TY][MX];
+  const int tx = threadIdx.x % MX, ty = threadIdx.x / MX;
+  const int gx = (a.nx + MX - 3) / (MX - 2), gy = (a.ny + TY - 3) / (TY - 2);
+  // tiles in x, then y, then the z-chunk
+  const int t = int(blockIdx.x);
   const int bxi = t % gx, byi = (t / gx) % gy, bz = t / (gx * gy);
-  const int x0 = bxi * (kMX - 2), y0 = byi * (TY - 2);
+  const int x0 = bxi * (MX - 2), y0 = byi * (TY - 2);
   // the patch node this thread rebuilds, and the node it updates if inner
   const int px = wrap(x0 - 1 + tx, a.nx), py = wrap(y0 - 1 + ty, a.ny);
-  const bool inner = tx >= 1 && tx <= kMX - 2 && ty >= 1 && ty <= TY - 2 && x0 + tx - 1 < a.nx && y0 + ty - 1 < a.ny;
+  const bool inner = tx >= 1 && tx <= MX - 2 && ty >= 1 && ty <= TY - 2 && x0 + tx - 1 < a.nx && y0 + ty - 1 < a.ny;
   const int64_t col_in = int64_t(py) * a.sy + px;
   const int64_t col_out = int64_t(y0 + ty - 1) * a.sy + (x0 + tx - 1);
   const R rho0 = R(a.rho0), om = R(a.omega1);
@@ -297,16 +301,16 @@ __global__ void __launch_bounds__(kMX * TY) k_mstep(const S* __restrict__ src, S
       lds_barrier();
       if (inner) {
         if constexpr (E == 1) {
-          add_layer<L, 1, TY, R>(next, pop, tx, ty);  // target z0
+          add_layer<L, 1, TY, MX, R>(next, pop, tx, ty);  // target z0
           cur = next;
           clear(next);
         } else if constexpr (E == -1) {
-          add_layer<L, -1, TY, R>(prev, pop, tx, ty);  // target z1 - 1 is complete
+          add_layer<L, -1, TY, MX, R>(prev, pop, tx, ty);  // target z1 - 1 is complete
           finalize_state<L, R>(prev, rho0, out);
         } else {
-          if (pz >= z0 + 1) add_layer<L, -1, TY, R>(prev, pop, tx, ty);
-          add_layer<L, 0, TY, R>(cur, pop, tx, ty);
-          if (pz + 1 < z1) add_layer<L, 1, TY, R>(next, pop, tx, ty);
+          if (pz >= z0 + 1) add_layer<L, -1, TY, MX, R>(prev, pop, tx, ty);
+          add_layer<L, 0, TY, MX, R>(cur, pop, tx, ty);
+          if (pz + 1 < z1) add_layer<L, 1, TY, MX, R>(next, pop, tx, ty);
           if (pz >= z0 + 1) finalize_state<L, R>(prev, rho0, out);  // target plane pz - 1 is complete
           prev = cur;
           cur = next;
@@ -515,16 +519,12 @@ __global__ void __launch_bounds__(256) k_mpopulations(const S* __restrict__ src,
 
 // ---------------------------------------------------------------------------
 // Launchers.  a.lz = z-planes per block of the 3D step (each chunk rebuilds
-// lz + 2 planes); the host picks it.
-// Patch rows: 16 for FP32 (a 55 KiB exchange), 8 for FP64 (the same bytes).
-// Measured on the 256^3 D3Q27 step (FP32, fields of a row together): 8, 16
-// and 32 rows within 6%; 4 z-planes per chunk best (36 GLUPS), 8 and more
-// 30% slower (larger planes want shorter chunks: the host's choice of lz);
-// dispatching the z-chunks of a tile next to each other gave 24-27 GLUPS at
-// 256^3 and 512^3 for lz = 2 to 32; padding the z-planes off multiples of
-// 64 KiB changed nothing.  Contiguous tile ranges per XCD (a.xcd_tiles) make
-// the rate nearly independent of lz and of the plane size; the host turns
-// them on for large planes (host side, moment_schedule).
+// lz + 2 planes); the host picks it.  Measured with 32 x 16 patches, 256^3
+// D3Q27 FP32: patches of 8, 16 and 32 rows within 6%; dispatching the z-chunks
+// of a tile next to each other gave 24-27 GLUPS at 256^3 and 512^3 for lz = 2
+// to 32; padding the z-planes off multiples of 64 KiB changed nothing;
+// contiguous tile ranges per XCD removed the fall-off at large planes but did
+// not beat the 64 x 8 patches in plain order.
 template <class L, int N, class S>
 hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream_t s) {
   if (a.lz < 1) return hipErrorInvalidValue;
@@ -535,12 +535,12 @@ hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream
                        static_cast<S*>(dst), a);
     return hipGetLastError();
   } else {
-    constexpr int TY = sizeof(S) == 4 ? 16 : 8;
-    const int64_t nb = int64_t((a.nx + kMX - 3) / (kMX - 2)) * ((a.ny + TY - 3) / (TY - 2)) *
+    constexpr int TY = MPatch<S>::TY, MX = MPatch<S>::MX;
+    const int64_t nb = int64_t((a.nx + MX - 3) / (MX - 2)) * ((a.ny + TY - 3) / (TY - 2)) *
                        ((a.nz + a.lz - 1) / a.lz);
     if (nb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mstep<L, N, S, TY>), dim3(unsigned(nb)), dim3(kMX * TY), 0, s, static_cast<const S*>(src),
-                       static_cast<S*>(dst), a);
+    hipLaunchKernelGGL((k_mstep<L, N, S, TY, MX>), dim3(unsigned(nb)), dim3(MX * TY), 0, s,
+                       static_cast<const S*>(src), static_cast<S*>(dst), a);
     return hipGetLastError();
   }
 }

@@ -19,7 +19,6 @@ struct StepArgs {
   double rho0;         // reference density of the deviation storage
   double omega1;       // 1 - 1/tau
   int lz;              // z-planes per block of the moment-state step (3D)
-  int xcd_tiles = 0;   // moment-state step (3D): contiguous tile ranges per XCD
 };
 
 struct LatticeOps {
