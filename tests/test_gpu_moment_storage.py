@@ -7,8 +7,9 @@ oracle (which stores populations) on the same seeded inputs:
 
   rho, u, pi1   same bars as the population storage (FP64 1e-12 / 1e-10,
                 FP32 1e-5 / 1e-4), every lattice and order, shapes that span
-                several blocks (30 x 6 target nodes per block) with ragged
-                tails and several z-chunks with a ragged last chunk;
+                several blocks (62 x 6 target nodes per FP32 block, 30 x 6
+                FP64) with ragged tails and several z-chunks with a ragged
+                last chunk;
   populations   the post-collision deviations rebuilt by lb_get_populations
                 equal the oracle's collide(f) - w rho0 (FP64: 1e-13 at t = 0,
                 the FP64 bar 1e-12 after three steps);
@@ -16,7 +17,8 @@ oracle (which stores populations) on the same seeded inputs:
                 totals and enstrophy of a 3D Taylor-Green run;
   chunking      the z-chunk length does not change a single bit;
   edges         boxes of 1 to 3 nodes along an axis (periodic images of one
-                node fill a block), block-boundary widths.
+                node fill a block), block-boundary widths of the FP64 and
+                FP32 tiles.
 """
 import numpy as np
 import pytest
@@ -142,6 +144,16 @@ def test_small_boxes_and_block_edges(lbrr, gpu, monkeypatch, lat):
         got = TP.gpu_run(lbrr, lat, 4, 0.66, shape, 3, 500 + k, "mom_fp64")
         e = errs(got, ref)
         assert e[0] <= 1e-12 and e[1] <= 1e-12 and e[2] <= 1e-10, (shape, e)
+    if L.D == 3:
+        # FP32 patches of 64 x 8 (inner 62 x 6): widths around one and two tiles, a tile
+        # with a few target columns, a box narrower than the patch
+        for k, shape in enumerate([(3, 5, 1), (2, 9, 2), (4, 7, 61), (3, 6, 62), (5, 7, 63), (2, 13, 64),
+                                   (3, 7, 124), (2, 9, 126), (3, 30, 67), (2, 61, 70), (3, 200, 3)]):
+            print(f"edges {lat} fp32 shape={shape}", flush=True)
+            ref = TP.oracle_run(lat, 4, 0.66, shape, 3, 600 + k)
+            got = TP.gpu_run(lbrr, lat, 4, 0.66, shape, 3, 600 + k, "mom_fp32")
+            e = errs(got, ref)
+            assert e[0] <= 1e-5 and e[1] <= 1e-5 and e[2] <= 1e-4, (shape, e)
 
 
 def test_moment_storage_refuses_population_input_and_closure(lbrr, gpu):
