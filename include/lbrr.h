@@ -129,10 +129,11 @@ int lb_step(lb_handle h, long long n);
  * equilibrium value (edges and corners); rho is the zeroth moment of the
  * completed set, a1^(2) its second moment minus rho c_s^2 I, and the node
  * collides with (rho, u = 0, a1^(2)).  Velocities given to lb_init_fields on
- * wall nodes should be 0.  A walled axis needs at least 3 nodes; population
- * storage only, no learned closure (LB_ERR_UNSUPPORTED otherwise).
- * lb_enstrophy uses one-sided differences on the walls.  Takes effect at the
- * next lb_step. */
+ * wall nodes should be 0.  A walled axis needs at least 3 nodes.  Population
+ * and moment storage (a wall node of the moment state keeps rho - rho0,
+ * j = 0 and that a1^(2)); not with the learned closure (lb_step returns
+ * LB_ERR_UNSUPPORTED).  lb_enstrophy uses one-sided differences on the walls.
+ * Takes effect at the next lb_step. */
 int lb_set_walls(lb_handle h, int walls);
 
 /* Stability check interval k for lb_step (0 = never, the default). */

@@ -129,6 +129,7 @@ struct lb_ctx {
     a.rho0 = rho0;
     a.omega1 = 1.0 - 1.0 / tau;
     a.lz = moment() ? moment_lz(nvalues(), elem_size(storage)) : 1;
+    a.walls = moment() ? walls : 0;
     return a;
   }
   void release() {
@@ -332,7 +333,6 @@ int lb_set_walls(lb_handle h, int walls) {
   const int dims[3] = {h->nx, h->ny, h->nz};
   for (int k = 0; k < 3; ++k)
     if ((walls >> k & 1) && dims[k] < 3) return fail(LB_ERR_INVALID_ARG, "a walled axis needs at least 3 nodes");
-  if (walls && h->moment()) return fail(LB_ERR_UNSUPPORTED, "walls need population storage");
   h->walls = walls;
   return LB_OK;
 }
@@ -388,15 +388,14 @@ int lb_step(lb_handle h, long long n) {
   if (n < 0) return fail(LB_ERR_INVALID_ARG, "n must be >= 0");
   if (!h->ready) return fail(LB_ERR_STATE, "lb_step before lb_init_fields / lb_set_populations");
   if (h->closure_on && h->moment()) return fail(LB_ERR_UNSUPPORTED, "the learned closure needs population storage");
-  if (h->walls && (h->moment() || h->closure_on))
-    return fail(LB_ERR_UNSUPPORTED, "walls need population storage and no closure");
+  if (h->walls && h->closure_on) return fail(LB_ERR_UNSUPPORTED, "walls and the learned closure exclude each other");
   const StepArgs a = h->args();
   for (long long k = 0; k < n; ++k) {
     hipError_t e;
     if (h->closure_on)
       e = lbrr::closure_step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->cl_packed, h->cl_params,
                              h->cl_norm, h->stream);
-    else if (h->walls)
+    else if (h->walls && !h->moment())
       e = h->ops->step_walls(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->walls, h->stream);
     else
       e = h->ops->step(h->order, h->storage, h->buf[h->cur], h->buf[1 - h->cur], a, h->stream);

@@ -212,6 +212,110 @@ __device__ __forceinline__ void add_row(Moments<R>& s, const R (*pop)[BX], int t
   }
 }
 
+// ---- resting walls -----------------------------------------------------------
+// Resting no-slip walls on the first and last node of the axes in a.walls: the
+// regularised Dirichlet boundary of Sec. 3.7 with u = 0, as the population step
+// applies it.  At a wall node a population whose source lies outside the box is
+// unknown; it takes the value of its opposite if that one is known (the
+// off-equilibrium bounce-back at u = 0, where w_i = w_opp), else w_i (rho - rho0);
+// rho - rho0 follows from the zeroth moment of the completed set, the node keeps
+// j = 0, and a1^(2) is the second moment of the completed set minus
+// (rho - rho0) c_s^2 I.  Every step is linear in the arriving populations, so
+// their contributions are summed layer by layer as they arrive: a known
+// population whose opposite is unknown counts twice (at xi and at -xi: the
+// momentum cancels), and the buried ones enter when the node is finalised.
+
+// Side of the box along one axis: -1 (first node), +1 (last node), 0.
+__device__ __forceinline__ int wall_side(int walls, int bit, int v, int n) {
+  return (walls >> bit & 1) ? (v == 0 ? -1 : (v == n - 1 ? 1 : 0)) : 0;
+}
+
+// Does a population moving along (cx, cy, cz) arrive from outside the box?
+__device__ __forceinline__ bool from_outside(int sx, int sy, int sz, int cx, int cy, int cz) {
+  return (sx != 0 && cx == -sx) || (sy != 0 && cy == -sy) || (sz != 0 && cz == -sz);
+}
+
+// Contribution of the known population v moving along (cx, cy, cz) to the moment
+// sums of a wall node (sides sx, sy, sz).
+template <class R>
+__device__ __forceinline__ void add_known(Moments<R>& s, R v, int cx, int cy, int cz, int sx, int sy, int sz) {
+  const bool twice = from_outside(sx, sy, sz, -cx, -cy, -cz);
+  const R k = twice ? R(2) * v : v;
+  s.d0 = s.d0 + k;
+  if (!twice) {
+    s.jx = s.jx + R(cx) * v;
+    s.jy = s.jy + R(cy) * v;
+    s.jz = s.jz + R(cz) * v;
+  }
+  s.pxx = s.pxx + R(cx * cx) * k;
+  s.pyy = s.pyy + R(cy * cy) * k;
+  s.pzz = s.pzz + R(cz * cz) * k;
+  s.pxy = s.pxy + R(cx * cy) * k;
+  s.pxz = s.pxz + R(cx * cz) * k;
+  s.pyz = s.pyz + R(cy * cz) * k;
+}
+
+// Wall node: the populations of layer c_z = CZ arriving at inner node (tx, ty).
+template <class L, int CZ, int TY, int MX, class R>
+__device__ __forceinline__ void add_layer_walls(Moments<R>& s, const R (*pop)[TY][MX], int tx, int ty, int sx, int sy,
+                                                int sz) {
+  sfor<0, 3>([&](auto Y) {
+    sfor<0, 3>([&](auto X) {
+      constexpr int cx = int(X) - 1, cy = int(Y) - 1;
+      if constexpr (has_velocity<L>(cx, cy, CZ)) {
+        if (!from_outside(sx, sy, sz, cx, cy, CZ))
+          add_known(s, pop[velocity_index<L>(cx, cy, CZ)][ty - cy][tx - cx], cx, cy, CZ, sx, sy, sz);
+      }
+    });
+  });
+}
+
+// 2D wall node: the populations with c_y = CY rebuilt on one row arriving at inner node tx.
+template <class L, int CY, int BX, class R>
+__device__ __forceinline__ void add_row_walls(Moments<R>& s, const R (*pop)[BX], int tx, int sx, int sy) {
+  sfor<0, 3>([&](auto X) {
+    constexpr int cx = int(X) - 1;
+    if (!from_outside(sx, sy, 0, cx, CY, 0)) add_known(s, pop[velocity_index<L>(cx, CY, 0)][tx - cx], cx, CY, 0, sx, sy, 0);
+  });
+}
+
+// Stored moments of a wall node from its sums (known and bounced populations).
+template <class L, class R>
+__device__ __forceinline__ void finalize_walls(const Moments<R>& s, int sx, int sy, int sz, R (&m)[kNM<L>]) {
+  R wb = R(0), bxx = R(0), byy = R(0), bzz = R(0), bxy = R(0), bxz = R(0), byz = R(0);  // buried: sum w, w xi xi
+  sfor<0, L::Q>([&](auto I) {
+    constexpr int cx = L::cx(I), cy = L::cy(I), cz = L::cz(I);
+    if (from_outside(sx, sy, sz, cx, cy, cz) && from_outside(sx, sy, sz, -cx, -cy, -cz)) {
+      const R w = R(L::w(I));
+      wb = wb + w;
+      bxx = bxx + R(cx * cx) * w;
+      byy = byy + R(cy * cy) * w;
+      bzz = bzz + R(cz * cz) * w;
+      bxy = bxy + R(cx * cy) * w;
+      bxz = bxz + R(cx * cz) * w;
+      byz = byz + R(cy * cz) * w;
+    }
+  });
+  const R drho = s.d0 / (R(1) - wb);
+  constexpr R cs2 = R(kCs2);
+  m[0] = drho;
+  m[1] = R(0);
+  m[2] = R(0);
+  if constexpr (L::D == 3) {
+    m[3] = R(0);
+    m[4] = s.pxx + drho * bxx - drho * cs2;
+    m[5] = s.pyy + drho * byy - drho * cs2;
+    m[6] = s.pzz + drho * bzz - drho * cs2;
+    m[7] = s.pxy + drho * bxy;
+    m[8] = s.pxz + drho * bxz;
+    m[9] = s.pyz + drho * byz;
+  } else {
+    m[3] = s.pxx + drho * bxx - drho * cs2;
+    m[4] = s.pyy + drho * byy - drho * cs2;
+    m[5] = s.pxy + drho * bxy;
+  }
+}
+
 // Block barrier for the LDS exchange: waits for the LDS accesses of every
 // wave but leaves global loads and stores in flight (threads of a block share
 // nothing through global memory here), so a prefetch survives the barrier.
@@ -227,7 +331,7 @@ __device__ __forceinline__ int wrap(int v, int n) {
 }
 
 // One step of the moment-state update (see the file comment).
-template <class L, int N, class S, int TY, int MX>
+template <class L, int N, class S, int TY, int MX, bool W>
 __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
   static_assert(L::D == 3, "3D lattices; 2D runs k_mstep2");
   using R = S;
@@ -267,6 +371,34 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
     S* d = dst + int64_t(z) * a.sz + col_out;
     sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], d + int64_t(C) * a.si); });
   };
+  // walls (W): sides of this thread's target column and row; the side along z
+  // depends on the target plane
+  const int wsx = W ? wall_side(a.walls, 0, x0 + tx - 1, a.nx) : 0;
+  const int wsy = W ? wall_side(a.walls, 1, y0 + ty - 1, a.ny) : 0;
+  auto add = [&](Moments<R>& sums, auto CZS, int target) __attribute__((always_inline)) {
+    constexpr int CZ = decltype(CZS)::value;
+    if constexpr (W) {
+      const int wsz = wall_side(a.walls, 2, target, a.nz);
+      if (wsx != 0 || wsy != 0 || wsz != 0) {
+        add_layer_walls<L, CZ, TY, MX, R>(sums, pop, tx, ty, wsx, wsy, wsz);
+        return;
+      }
+    }
+    add_layer<L, CZ, TY, MX, R>(sums, pop, tx, ty);
+  };
+  auto finish = [&](const Moments<R>& sums, int target, R (&m)[NM]) __attribute__((always_inline)) {
+    if constexpr (W) {
+      const int wsz = wall_side(a.walls, 2, target, a.nz);
+      if (wsx != 0 || wsy != 0 || wsz != 0) {
+        finalize_walls<L, R>(sums, wsx, wsy, wsz, m);
+        return;
+      }
+    }
+    finalize_state<L, R>(sums, rho0, m);
+  };
+  using layer_m = std::integral_constant<int, -1>;
+  using layer_0 = std::integral_constant<int, 0>;
+  using layer_p = std::integral_constant<int, 1>;
 
   {
     // Target planes z0 .. z1-1; planes z0-1 .. z1 are rebuilt.  Plane z0-1
@@ -301,17 +433,17 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
       lds_barrier();
       if (inner) {
         if constexpr (E == 1) {
-          add_layer<L, 1, TY, MX, R>(next, pop, tx, ty);  // target z0
+          add(next, layer_p{}, z0);  // target z0
           cur = next;
           clear(next);
         } else if constexpr (E == -1) {
-          add_layer<L, -1, TY, MX, R>(prev, pop, tx, ty);  // target z1 - 1 is complete
-          finalize_state<L, R>(prev, rho0, out);
+          add(prev, layer_m{}, z1 - 1);  // target z1 - 1 is complete
+          finish(prev, z1 - 1, out);
         } else {
-          if (pz >= z0 + 1) add_layer<L, -1, TY, MX, R>(prev, pop, tx, ty);
-          add_layer<L, 0, TY, MX, R>(cur, pop, tx, ty);
-          if (pz + 1 < z1) add_layer<L, 1, TY, MX, R>(next, pop, tx, ty);
-          if (pz >= z0 + 1) finalize_state<L, R>(prev, rho0, out);  // target plane pz - 1 is complete
+          if (pz >= z0 + 1) add(prev, layer_m{}, pz - 1);
+          add(cur, layer_0{}, pz);
+          if (pz + 1 < z1) add(next, layer_p{}, pz + 1);
+          if (pz >= z0 + 1) finish(prev, pz - 1, out);  // target plane pz - 1 is complete
           prev = cur;
           cur = next;
           clear(next);
@@ -346,7 +478,7 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
 // been rebuilt.  Rows of BX nodes keep the loads and stores of a field nearly
 // line-aligned (one partial 128-byte line per row and field), and the two-stage
 // prefetch ring of the 3D step overlaps them with the rebuilds.
-template <class L, int N, class S, int BX>
+template <class L, int N, class S, int BX, bool W>
 __global__ void __launch_bounds__(BX) k_mstep2(const S* __restrict__ src, S* __restrict__ dst, StepArgs a) {
   using R = S;
   constexpr int NM = kNM<L>;
@@ -392,10 +524,27 @@ __global__ void __launch_bounds__(BX) k_mstep2(const S* __restrict__ src, S* __r
     }
     lds_barrier();
     if (inner) {
-      add_row<L, -1, BX, R>(prev, pop, tx);
-      add_row<L, 0, BX, R>(cur, pop, tx);
-      add_row<L, 1, BX, R>(next, pop, tx);
-      if (py >= y0 + 1) finalize_state<L, R>(prev, rho0, out);  // target row py - 1 is complete
+      bool plain = true;
+      if constexpr (W) {
+        // walls: sides of the target column and of the target rows py - 1, py, py + 1
+        // (with no side the wall sums are the plain sums)
+        plain = false;
+        const int sx = wall_side(a.walls, 0, xo, a.nx);
+        const int sm = wall_side(a.walls, 1, wrap(py - 1, a.ny), a.ny);
+        add_row_walls<L, -1, BX, R>(prev, pop, tx, sx, sm);
+        add_row_walls<L, 0, BX, R>(cur, pop, tx, sx, wall_side(a.walls, 1, wrap(py, a.ny), a.ny));
+        add_row_walls<L, 1, BX, R>(next, pop, tx, sx, wall_side(a.walls, 1, wrap(py + 1, a.ny), a.ny));
+        if (py >= y0 + 1) {  // target row py - 1 is complete
+          if (sx != 0 || sm != 0) finalize_walls<L, R>(prev, sx, sm, 0, out);
+          else finalize_state<L, R>(prev, rho0, out);
+        }
+      }
+      if (plain) {
+        add_row<L, -1, BX, R>(prev, pop, tx);
+        add_row<L, 0, BX, R>(cur, pop, tx);
+        add_row<L, 1, BX, R>(next, pop, tx);
+        if (py >= y0 + 1) finalize_state<L, R>(prev, rho0, out);  // target row py - 1 is complete
+      }
       prev = cur;
       cur = next;
       clear(next);
@@ -531,16 +680,24 @@ hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream
   if constexpr (L::D == 2) {
     dim3 grid2(unsigned((a.nx + kRowX - 3) / (kRowX - 2)), unsigned((a.ny + a.lz - 1) / a.lz));
     if (grid2.y > 65535u) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mstep2<L, N, S, kRowX>), grid2, dim3(kRowX), 0, s, static_cast<const S*>(src),
-                       static_cast<S*>(dst), a);
+    if (a.walls)
+      hipLaunchKernelGGL((k_mstep2<L, N, S, kRowX, true>), grid2, dim3(kRowX), 0, s, static_cast<const S*>(src),
+                         static_cast<S*>(dst), a);
+    else
+      hipLaunchKernelGGL((k_mstep2<L, N, S, kRowX, false>), grid2, dim3(kRowX), 0, s, static_cast<const S*>(src),
+                         static_cast<S*>(dst), a);
     return hipGetLastError();
   } else {
     constexpr int TY = MPatch<S>::TY, MX = MPatch<S>::MX;
     const int64_t nb = int64_t((a.nx + MX - 3) / (MX - 2)) * ((a.ny + TY - 3) / (TY - 2)) *
                        ((a.nz + a.lz - 1) / a.lz);
     if (nb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mstep<L, N, S, TY, MX>), dim3(unsigned(nb)), dim3(MX * TY), 0, s,
-                       static_cast<const S*>(src), static_cast<S*>(dst), a);
+    if (a.walls)
+      hipLaunchKernelGGL((k_mstep<L, N, S, TY, MX, true>), dim3(unsigned(nb)), dim3(MX * TY), 0, s,
+                         static_cast<const S*>(src), static_cast<S*>(dst), a);
+    else
+      hipLaunchKernelGGL((k_mstep<L, N, S, TY, MX, false>), dim3(unsigned(nb)), dim3(MX * TY), 0, s,
+                         static_cast<const S*>(src), static_cast<S*>(dst), a);
     return hipGetLastError();
   }
 }

@@ -19,6 +19,7 @@ struct StepArgs {
   double rho0;         // reference density of the deviation storage
   double omega1;       // 1 - 1/tau
   int lz;              // z-planes per block of the moment-state step (3D)
+  int walls;           // moment-state step: resting walls on the axes of this mask (bit 0 x, 1 y, 2 z)
 };
 
 struct LatticeOps {

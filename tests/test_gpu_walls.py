@@ -2,9 +2,9 @@
 
 Against the FP64 oracle (`oracle/walls.py`) on the same seeded inputs, with the velocity set to 0
 on the wall nodes: rho, u, pi1 after several steps for every lattice and order, walls on one,
-two or three axes (edges and corners included), FP64 bar 1e-12 / 1e-10, FP32 1e-5 / 1e-4;
-enstrophy with one-sided wall differences; the rest state of a closed box; the channel shear mode
-decay rate on the GPU; argument checks.
+two or three axes (edges and corners included), population and moment storage, FP64 bar
+1e-12 / 1e-10, FP32 1e-5 / 1e-4; enstrophy with one-sided wall differences; the rest state of a
+closed box; the channel shear mode decay rate on the GPU; argument checks.
 """
 import numpy as np
 import pytest
@@ -16,7 +16,7 @@ from oracle import walls as OW
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-5, 1e-4)}
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-5, 1e-4), "mom_fp64": (1e-12, 1e-10), "mom_fp32": (1e-5, 1e-4)}
 WALLS = {2: [(True, True, False), (False, True, False), (True, False, False)],
          3: [(True, True, True), (False, True, False), (True, True, False)]}
 SHAPES = {2: (1, 23, 300), 3: (7, 9, 70)}
@@ -60,7 +60,7 @@ def gpu_walls(P, lat, N, tau, shape, walls, steps, seed, storage):
     return r, v, p, ens
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "mom_fp64", "mom_fp32"])
 @pytest.mark.parametrize("lat,N", TP.CASES)
 def test_walls_parity_with_oracle(lbrr, gpu, lat, N, storage):
     L = OL.lattice(lat)
@@ -75,14 +75,15 @@ def test_walls_parity_with_oracle(lbrr, gpu, lat, N, storage):
         e_ens = abs(got[3] - ref[3]) / ref[3]
         print(f"  err rho {e[0]:.2e} u {e[1]:.2e} pi1 {e[2]:.2e} enstrophy {e_ens:.2e}", flush=True)
         assert e[0] <= tol_ru and e[1] <= tol_ru and e[2] <= tol_pi
-        assert e_ens <= (1e-12 if storage == "fp64" else 1e-4)
+        assert e_ens <= (1e-12 if storage.endswith("fp64") else 1e-4)
 
 
+@pytest.mark.parametrize("storage", ["fp64", "mom_fp64"])
 @pytest.mark.parametrize("lat", ["D2Q9", "D3Q19", "D3Q27"])
-def test_rest_in_a_closed_box(lbrr, gpu, lat):
+def test_rest_in_a_closed_box(lbrr, gpu, lat, storage):
     L = OL.lattice(lat)
     shape = (5, 6, 7) if L.D == 3 else (1, 9, 7)
-    sim = lbrr.Simulation(lat, shape, 0.7, 4, storage="fp64")
+    sim = lbrr.Simulation(lat, shape, 0.7, 4, storage=storage)
     sim.set_walls(True, True, L.D == 3)
     sim.init_fields(np.full(shape, 1.02), np.zeros((L.D,) + shape))
     sim.step(10)
@@ -121,5 +122,5 @@ def test_wall_arguments_are_checked(lbrr, gpu):
     assert lbrr.lb_set_walls(sim.handle, 2) == lbrr.LB_OK
     sim.close()
     sim = lbrr.Simulation("D3Q27", (4, 4, 4), 0.7, 4, storage="mom_fp32")
-    assert lbrr.lb_set_walls(sim.handle, 1) == lbrr.LB_ERR_UNSUPPORTED
+    assert lbrr.lb_set_walls(sim.handle, 7) == lbrr.LB_OK  # moment storage takes walls too
     sim.close()
