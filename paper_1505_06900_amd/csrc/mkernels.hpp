@@ -325,6 +325,16 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Element at a byte offset from a base pointer.
+template <class S>
+__device__ __forceinline__ S at_offset(const S* base, uint32_t off) {
+  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(base) + off);
+}
+template <class S>
+__device__ __forceinline__ S* ptr_at_offset(S* base, uint32_t off) {
+  return reinterpret_cast<S*>(reinterpret_cast<char*>(base) + off);
+}
+
 __device__ __forceinline__ int wrap(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
@@ -346,13 +356,16 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
   // the patch node this thread rebuilds, and the node it updates if inner
   const int px = wrap(x0 - 1 + tx, a.nx), py = wrap(y0 - 1 + ty, a.ny);
   const bool inner = tx >= 1 && tx <= MX - 2 && ty >= 1 && ty <= TY - 2 && x0 + tx - 1 < a.nx && y0 + ty - 1 < a.ny;
-  const int64_t col_in = int64_t(py) * a.sy + px;
-  const int64_t col_out = int64_t(y0 + ty - 1) * a.sy + (x0 + tx - 1);
+  // Byte offsets of the node within its plane of one field (32 bits: the host
+  // checks that a plane fits); the plane and field bases are block-uniform, so
+  // each access is a scalar base plus one per-lane 32-bit offset.
+  const uint32_t off_in = uint32_t((int64_t(py) * a.sy + px) * int64_t(sizeof(S)));
+  const uint32_t off_out = uint32_t((int64_t(y0 + ty - 1) * a.sy + (x0 + tx - 1)) * int64_t(sizeof(S)));
   const R rho0 = R(a.rho0), om = R(a.omega1);
 
   auto load = [&](int z, R (&m)[NM]) {
-    const S* s = src + int64_t(z) * a.sz + col_in;
-    sfor<0, NM>([&](auto C) { m[C] = s[int64_t(C) * a.si]; });
+    const S* s = src + int64_t(z) * a.sz;
+    sfor<0, NM>([&](auto C) { m[C] = at_offset(s + int64_t(C) * a.si, off_in); });
   };
   // Rebuild the populations of this thread's patch node into LDS; ZS selects
   // all of them (2) or only those with c_z = ZS (the planes next to a chunk).
@@ -368,8 +381,8 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
     });
   };
   auto put = [&](int z, const R (&m)[NM]) {
-    S* d = dst + int64_t(z) * a.sz + col_out;
-    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], d + int64_t(C) * a.si); });
+    S* d = dst + int64_t(z) * a.sz;
+    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], ptr_at_offset(d + int64_t(C) * a.si, off_out)); });
   };
   // walls (W): sides of this thread's target column and row; the side along z
   // depends on the target plane
@@ -689,6 +702,7 @@ hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream
     return hipGetLastError();
   } else {
     constexpr int TY = MPatch<S>::TY, MX = MPatch<S>::MX;
+    if (int64_t(a.ny) * a.sy * int64_t(sizeof(S)) >= (int64_t(1) << 32)) return hipErrorInvalidValue;
     const int64_t nb = int64_t((a.nx + MX - 3) / (MX - 2)) * ((a.ny + TY - 3) / (TY - 2)) *
                        ((a.nz + a.lz - 1) / a.lz);
     if (nb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
