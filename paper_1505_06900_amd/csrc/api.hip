@@ -53,20 +53,24 @@ size_t elem_size(int storage) {
 // Chunk length of the moment-state step: rows per block in 2D, z-planes per
 // block in 3D (each block rebuilds lz + 2).  Measured on MI355X:
 //   2D, rows of 256 nodes: 4 rows best (see kRowX).
-//   3D FP32, 64 x 8 patches, D3Q27 (GLUPS at lz = 4 / 6 / 8 / 12 / 16 / 32):
-//     256^3 36.1 / 37.1 / 37.4 / 38.1 / 37.2 / 33.7
-//     384^3 38.5 / 39.8 / 39.9 / 38.3 / 36.5 / 35.0
-//     512^3 39.5 / 40.8 / 41.0 / 37.4 / 36.5 / 35.3
-//   and D3Q19 order 3 ran 37-43 at 6 but 33-36 at 8: FP32 takes 6.
-//   3D FP64, 32 x 8 patches: 4 (19-21 GLUPS at 256^3 and 384^3, 16.5 at 2).
+//   3D, 64 x 8 (FP32) or 32 x 8 (FP64) patches, march unrolled by 3, GLUPS at
+//   lz = 3 / 4 / 6 / 9 / 12:
+//     D3Q27 FP32 256^3 37.1 / 38.6 / 39.9 / 39.2 / 39.6
+//                384^3 38.5 / 39.9 / 41.8 / 39.5 / 37.2
+//                512^3 40.5 / 41.9 / 42.6 / 37.7 / 36.9
+//     D3Q19 order 3 FP32 (lz = 4 / 6 / 9): 256^3 41.1 / 42.0 / 40.5,
+//                384^3 41.4 / 42.4 / 38.3, 512^3 44.6 / 37.9 / 36.2
+//     D3Q27 FP64 (lz = 3 / 4 / 6): 256^3 20.8 / 21.4 / 22.0, 512^3 19.8 / 20.3 / 21.7
+//   So lz = 6, except D3Q19 on planes of 512^2 nodes and more: 4.
 // LBRR_MOM_LZ overrides the choice.
-int moment_lz(int nvalues, size_t es) {
+int moment_lz(int nvalues, int q, int64_t plane_nodes) {
   if (const char* e = std::getenv("LBRR_MOM_LZ")) {
     const int v = std::atoi(e);
     if (v >= 1) return v;
   }
   if (nvalues == 6) return 4;
-  return es == 4 ? 6 : 4;
+  if (q == 19 && plane_nodes >= 512 * 512) return 4;
+  return 6;
 }
 
 // Extra bytes after each population plane (layouts 0 and 2).  Planes whose
@@ -128,7 +132,7 @@ struct lb_ctx {
     a.sz = sz;
     a.rho0 = rho0;
     a.omega1 = 1.0 - 1.0 / tau;
-    a.lz = moment() ? moment_lz(nvalues(), elem_size(storage)) : 1;
+    a.lz = moment() ? moment_lz(nvalues(), q(), int64_t(nx) * ny) : 1;
     a.walls = moment() ? walls : 0;
     return a;
   }

@@ -138,7 +138,7 @@ constexpr int velocity_index(int cx, int cy, int cz) {
 // Add the populations of the layer c_z = CZ that arrive at inner node (tx, ty)
 // to its moment sums s: population (cx, cy, CZ) comes from patch node
 // (tx - cx, ty - cy).  Sums along x, then y, then the c_z factors.
-template <class L, int CZ, int TY, int MX, class R>
+template <class L, int CZ, int TY, int MX, class R, bool Assign = false>
 __device__ __forceinline__ void add_layer(Moments<R>& s, const R (*pop)[TY][MX], int tx, int ty) {
   R r0[3], r1[3], r2[3];  // per row cy: sum of v, cx v, cx^2 v
   sfor<0, 3>([&](auto Y) {
@@ -165,6 +165,20 @@ __device__ __forceinline__ void add_layer(Moments<R>& s, const R (*pop)[TY][MX],
   const R s00 = e0 + r0[1], s01 = r0[2] - r0[0], s02 = e0;
   const R s10 = (r1[2] + r1[0]) + r1[1], s11 = r1[2] - r1[0];
   const R s20 = (r2[2] + r2[0]) + r2[1];
+  if constexpr (Assign) {  // the first layer a target receives (c_z = +1) sets every sum
+    static_assert(CZ > 0, "assign with the c_z = +1 layer");
+    s.d0 = s00;
+    s.jx = s10;
+    s.jy = s01;
+    s.pxx = s20;
+    s.pyy = s02;
+    s.pxy = s11;
+    s.pzz = s00;
+    s.jz = s00;
+    s.pxz = s10;
+    s.pyz = s01;
+    return;
+  }
   s.d0 = s.d0 + s00;
   s.jx = s.jx + s10;
   s.jy = s.jy + s01;
@@ -388,16 +402,19 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
   // depends on the target plane
   const int wsx = W ? wall_side(a.walls, 0, x0 + tx - 1, a.nx) : 0;
   const int wsy = W ? wall_side(a.walls, 1, y0 + ty - 1, a.ny) : 0;
+  // Add layer c_z = CZ to the sums of target plane `target`; the c_z = +1 layer
+  // is the first a target receives and sets the sums.
   auto add = [&](Moments<R>& sums, auto CZS, int target) __attribute__((always_inline)) {
     constexpr int CZ = decltype(CZS)::value;
     if constexpr (W) {
       const int wsz = wall_side(a.walls, 2, target, a.nz);
       if (wsx != 0 || wsy != 0 || wsz != 0) {
+        if constexpr (CZ > 0) clear(sums);
         add_layer_walls<L, CZ, TY, MX, R>(sums, pop, tx, ty, wsx, wsy, wsz);
         return;
       }
     }
-    add_layer<L, CZ, TY, MX, R>(sums, pop, tx, ty);
+    add_layer<L, CZ, TY, MX, R, (CZ > 0)>(sums, pop, tx, ty);
   };
   auto finish = [&](const Moments<R>& sums, int target, R (&m)[NM]) __attribute__((always_inline)) {
     if constexpr (W) {
@@ -414,70 +431,74 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
   using layer_p = std::integral_constant<int, 1>;
 
   {
-    // Target planes z0 .. z1-1; planes z0-1 .. z1 are rebuilt.  Plane z0-1
-    // reaches only target z0 (its c_z = +1 populations) and plane z1 only
-    // target z1-1 (c_z = -1), so those two rebuild a third of the populations
-    // and add one layer.  The moments of a completed target plane are kept in
-    // registers and stored at the start of the next iteration, next to the
-    // prefetch of the plane kPrefetch ahead: loads and stores then have one or
-    // more whole rebuilds to complete before they are waited for.
-    static_assert(kPrefetch == 2, "the buffer rotation below assumes two planes in flight");
+    // Target planes z0 .. z1-1; planes z0-1 .. z1 are rebuilt, plane k of the
+    // march being z0 - 1 + k (k = 0 .. n + 1, n = z1 - z0).  Plane 0 reaches only
+    // target z0 (its c_z = +1 populations) and plane n + 1 only target z1 - 1
+    // (c_z = -1), so those two rebuild a third of the populations and add one
+    // layer.  Plane k adds its c_z = +1 layer to target k (first contribution),
+    // c_z = 0 to target k - 1 and c_z = -1 to target k - 2, which is then
+    // complete.  Roles rotate with period 3: the moments of plane k sit in
+    // buffer k mod 3 (plane k + 2 is loaded into buffer (k + 2) mod 3 while plane
+    // k is rebuilt) and the sums of target j in T[j mod 3]; the march is unrolled
+    // by 3, so no register is copied between iterations.  The moments of a
+    // completed target are kept in registers and stored at the start of the next
+    // iteration, next to the prefetch: loads and stores then have one or more
+    // whole rebuilds to complete before they are waited for.
+    static_assert(kPrefetch == 2, "two planes in flight ahead of the rebuild");
     const int z0 = bz * a.lz;
     const int z1 = (z0 + a.lz < a.nz) ? z0 + a.lz : a.nz;
-    Moments<R> prev, cur, next;  // sums of target planes p-1, p, p+1
-    clear(prev);
-    clear(cur);
-    clear(next);
-    // Moments of the planes to rebuild, two planes in flight: plane p sits in
-    // buffer (p - z0 + 1) mod 2, which is refilled with plane p + 2 as soon as
-    // its contents are taken.
-    R pre[kPrefetch][NM];
-    load(wrap(z0 - 1, a.nz), pre[0]);
-    load(wrap(z0, a.nz), pre[1]);
-    R out[NM];  // moments of target plane pz - 2, stored during iteration pz
-    // E = 2: plane inside the chunk; +1: plane z0 - 1; -1: plane z1.
-    auto iteration = [&](int pz, R (&buf)[NM], auto ES) __attribute__((always_inline)) {
-      constexpr int E = decltype(ES)::value;
-      R m[NM];
-      sfor<0, NM>([&](auto C) { m[C] = buf[C]; });
-      if (pz + kPrefetch <= z1) load(wrap(pz + kPrefetch, a.nz), buf);
-      if (inner && pz >= z0 + 2) put(pz - 2, out);
-      rebuild(m, ES);
+    const int n = z1 - z0;
+    Moments<R> T[3];  // sums of targets j = k, k - 1, k - 2 (mod 3) at plane k
+    R B[3][NM];       // moments of planes k, k + 1, k + 2 (mod 3)
+    load(wrap(z0 - 1, a.nz), B[0]);
+    load(wrap(z0, a.nz), B[1]);
+    R out[NM];  // moments of target k - 3, stored during plane k
+    // E = 2: plane inside the chunk; +1: plane 0; -1: plane n + 1.  PH = k mod 3.
+    auto iteration = [&](int k, auto PHS, auto ES) __attribute__((always_inline)) {
+      constexpr int PH = decltype(PHS)::value, E = decltype(ES)::value;
+      constexpr int P1 = (PH + 2) % 3, P2 = (PH + 1) % 3;  // (k - 1) mod 3, (k - 2) mod 3
+      const int pz = z0 - 1 + k;
+      if (k + kPrefetch <= n + 1) load(wrap(pz + kPrefetch, a.nz), B[P1]);  // buffer (k + 2) mod 3
+      if (inner && k >= 3) put(z0 + k - 3, out);
+      rebuild(B[PH], ES);
       lds_barrier();
       if (inner) {
         if constexpr (E == 1) {
-          add(next, layer_p{}, z0);  // target z0
-          cur = next;
-          clear(next);
+          add(T[PH], layer_p{}, z0);  // target z0 (k = 0)
         } else if constexpr (E == -1) {
-          add(prev, layer_m{}, z1 - 1);  // target z1 - 1 is complete
-          finish(prev, z1 - 1, out);
+          add(T[P2], layer_m{}, z1 - 1);  // target n - 1 = k - 2 is complete
+          finish(T[P2], z1 - 1, out);
         } else {
-          if (pz >= z0 + 1) add(prev, layer_m{}, pz - 1);
-          add(cur, layer_0{}, pz);
-          if (pz + 1 < z1) add(next, layer_p{}, pz + 1);
-          if (pz >= z0 + 1) finish(prev, pz - 1, out);  // target plane pz - 1 is complete
-          prev = cur;
-          cur = next;
-          clear(next);
+          if (k < n) add(T[PH], layer_p{}, pz + 1);
+          add(T[P1], layer_0{}, pz);
+          if (k >= 2) {
+            add(T[P2], layer_m{}, pz - 1);
+            finish(T[P2], pz - 1, out);  // target k - 2 is complete
+          }
         }
       }
       lds_barrier();
     };
+    using ph0 = std::integral_constant<int, 0>;
+    using ph1 = std::integral_constant<int, 1>;
+    using ph2 = std::integral_constant<int, 2>;
     using first_plane = std::integral_constant<int, 1>;
     using inner_plane = std::integral_constant<int, 2>;
     using last_plane = std::integral_constant<int, -1>;
-    iteration(z0 - 1, pre[0], first_plane{});
-    int pz = z0;
-    for (; pz + 1 < z1; pz += 2) {
-      iteration(pz, pre[1], inner_plane{});
-      iteration(pz + 1, pre[0], inner_plane{});
+    iteration(0, ph0{}, first_plane{});
+    int k = 1;
+    for (; k + 2 <= n; k += 3) {
+      iteration(k, ph1{}, inner_plane{});
+      iteration(k + 1, ph2{}, inner_plane{});
+      iteration(k + 2, ph0{}, inner_plane{});
     }
-    if (pz < z1) {  // one inner plane left: pz = z1 - 1, then z1 in buffer 0
-      iteration(pz, pre[1], inner_plane{});
-      iteration(z1, pre[0], last_plane{});
-    } else {  // pz = z1, in buffer 1
-      iteration(z1, pre[1], last_plane{});
+    if (k <= n) iteration(k++, ph1{}, inner_plane{});  // k = 1 mod 3 here
+    if (k <= n) iteration(k++, ph2{}, inner_plane{});
+    // k = n + 1: the last plane
+    switch (k % 3) {
+      case 0: iteration(k, ph0{}, last_plane{}); break;
+      case 1: iteration(k, ph1{}, last_plane{}); break;
+      default: iteration(k, ph2{}, last_plane{}); break;
     }
     if (inner) put(z1 - 1, out);
   }
