@@ -202,7 +202,7 @@ __device__ __forceinline__ void add_layer(Moments<R>& s, const R (*pop)[TY][MX],
 // 2D: add the populations with c_y = CY rebuilt on one row that arrive at
 // inner node tx to its moment sums s: population (cx, CY) comes from row node
 // tx - cx.
-template <class L, int CY, int BX, class R>
+template <class L, int CY, int BX, class R, bool Assign = false>
 __device__ __forceinline__ void add_row(Moments<R>& s, const R (*pop)[BX], int tx) {
   R v[3];
   sfor<0, 3>([&](auto X) {
@@ -211,6 +211,17 @@ __device__ __forceinline__ void add_row(Moments<R>& s, const R (*pop)[BX], int t
   });
   const R e = v[2] + v[0];
   const R s0 = e + v[1], s1 = v[2] - v[0];
+  if constexpr (Assign) {  // the first row a target receives (c_y = +1) sets every sum
+    static_assert(CY > 0, "assign with the c_y = +1 row");
+    s.d0 = s0;
+    s.jx = s1;
+    s.pxx = e;
+    s.pyy = s0;
+    s.jy = s0;
+    s.pxy = s1;
+    s.jz = s.pzz = s.pxz = s.pyz = R(0);
+    return;
+  }
   s.d0 = s.d0 + s0;
   s.jx = s.jx + s1;
   s.pxx = s.pxx + e;
@@ -524,32 +535,38 @@ __global__ void __launch_bounds__(BX) k_mstep2(const S* __restrict__ src, S* __r
   const bool inner = tx >= 1 && tx <= BX - 2 && x0 + tx - 1 < a.nx;
   const int xo = x0 + tx - 1;
   const R rho0 = R(a.rho0), om = R(a.omega1);
+  // byte offsets within a row of one field; row and field bases are block-uniform
+  const uint32_t off_in = uint32_t(px) * uint32_t(sizeof(S)), off_out = uint32_t(xo) * uint32_t(sizeof(S));
   auto load = [&](int y, R (&m)[NM]) {
-    const S* s = src + int64_t(y) * a.sy + px;
-    sfor<0, NM>([&](auto C) { m[C] = s[int64_t(C) * a.si]; });
+    const S* s = src + int64_t(y) * a.sy;
+    sfor<0, NM>([&](auto C) { m[C] = at_offset(s + int64_t(C) * a.si, off_in); });
   };
   auto put = [&](int y, const R (&m)[NM]) {
-    S* d = dst + int64_t(y) * a.sy + xo;
-    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], d + int64_t(C) * a.si); });
+    S* d = dst + int64_t(y) * a.sy;
+    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], ptr_at_offset(d + int64_t(C) * a.si, off_out)); });
   };
+  // Target rows y0 .. y1-1; rows y0-1 .. y1 are rebuilt, row k of the march
+  // being y0 - 1 + k (k = 0 .. n + 1, n = y1 - y0).  Row k adds its c_y = +1
+  // populations to target k (first contribution), c_y = 0 to target k - 1 and
+  // c_y = -1 to target k - 2, which is then complete.  Register roles rotate
+  // with period 3 as in the 3D step: moments of row k in buffer k mod 3, sums
+  // of target j in slot j mod 3, the march unrolled by 3 with no copies.
   const int y0 = blockIdx.y * a.lz;
   const int y1 = (y0 + a.lz < a.ny) ? y0 + a.lz : a.ny;
-  Moments<R> prev, cur, next;  // sums of target rows p-1, p, p+1
-  clear(prev);
-  clear(cur);
-  clear(next);
-  R pre[kPrefetch][NM];
-  sfor<0, kPrefetch>([&](auto K) {
-    if (y0 - 1 + int(K) <= y1) load(wrap(y0 - 1 + int(K), a.ny), pre[K]);
-  });
-  R out[NM];  // moments of target row py - 2, stored during iteration py
-  auto iteration = [&](int py, R (&buf)[NM]) __attribute__((always_inline)) {
-    R m[NM];
-    sfor<0, NM>([&](auto C) { m[C] = buf[C]; });
-    if (py + kPrefetch <= y1) load(wrap(py + kPrefetch, a.ny), buf);
-    if (inner && py >= y0 + 2) put(py - 2, out);
+  const int n = y1 - y0;
+  Moments<R> T[3];
+  R B[3][NM];
+  load(wrap(y0 - 1, a.ny), B[0]);
+  load(wrap(y0, a.ny), B[1]);
+  R out[NM];  // moments of target k - 3, stored during row k
+  auto iteration = [&](int k, auto PHS) __attribute__((always_inline)) {
+    constexpr int PH = decltype(PHS)::value;
+    constexpr int P1 = (PH + 2) % 3, P2 = (PH + 1) % 3;  // (k - 1) mod 3, (k - 2) mod 3
+    const int py = y0 - 1 + k;
+    if (k + kPrefetch <= n + 1) load(wrap(py + kPrefetch, a.ny), B[P1]);  // buffer (k + 2) mod 3
+    if (inner && k >= 3) put(y0 + k - 3, out);
     {
-      const Hydro<R> h = state_hydro<L, R>(m, rho0);
+      const Hydro<R> h = state_hydro<L, R>(B[PH], rho0);
       R C[3][3][3];
       coefficients<L, N, R>(h, om, C);
       R f[L::Q];
@@ -558,38 +575,44 @@ __global__ void __launch_bounds__(BX) k_mstep2(const S* __restrict__ src, S* __r
     }
     lds_barrier();
     if (inner) {
-      bool plain = true;
       if constexpr (W) {
-        // walls: sides of the target column and of the target rows py - 1, py, py + 1
+        // walls: sides of the target column and of the target rows py + 1, py, py - 1
         // (with no side the wall sums are the plain sums)
-        plain = false;
         const int sx = wall_side(a.walls, 0, xo, a.nx);
-        const int sm = wall_side(a.walls, 1, wrap(py - 1, a.ny), a.ny);
-        add_row_walls<L, -1, BX, R>(prev, pop, tx, sx, sm);
-        add_row_walls<L, 0, BX, R>(cur, pop, tx, sx, wall_side(a.walls, 1, wrap(py, a.ny), a.ny));
-        add_row_walls<L, 1, BX, R>(next, pop, tx, sx, wall_side(a.walls, 1, wrap(py + 1, a.ny), a.ny));
-        if (py >= y0 + 1) {  // target row py - 1 is complete
-          if (sx != 0 || sm != 0) finalize_walls<L, R>(prev, sx, sm, 0, out);
-          else finalize_state<L, R>(prev, rho0, out);
+        if (k < n) {
+          clear(T[PH]);
+          add_row_walls<L, 1, BX, R>(T[PH], pop, tx, sx, wall_side(a.walls, 1, py + 1, a.ny));
+        }
+        if (k >= 1 && k <= n) add_row_walls<L, 0, BX, R>(T[P1], pop, tx, sx, wall_side(a.walls, 1, py, a.ny));
+        if (k >= 2) {  // target row py - 1 is complete
+          const int sm = wall_side(a.walls, 1, py - 1, a.ny);
+          add_row_walls<L, -1, BX, R>(T[P2], pop, tx, sx, sm);
+          if (sx != 0 || sm != 0) finalize_walls<L, R>(T[P2], sx, sm, 0, out);
+          else finalize_state<L, R>(T[P2], rho0, out);
+        }
+      } else {
+        if (k < n) add_row<L, 1, BX, R, true>(T[PH], pop, tx);
+        if (k >= 1 && k <= n) add_row<L, 0, BX, R>(T[P1], pop, tx);
+        if (k >= 2) {
+          add_row<L, -1, BX, R>(T[P2], pop, tx);
+          finalize_state<L, R>(T[P2], rho0, out);  // target row py - 1 is complete
         }
       }
-      if (plain) {
-        add_row<L, -1, BX, R>(prev, pop, tx);
-        add_row<L, 0, BX, R>(cur, pop, tx);
-        add_row<L, 1, BX, R>(next, pop, tx);
-        if (py >= y0 + 1) finalize_state<L, R>(prev, rho0, out);  // target row py - 1 is complete
-      }
-      prev = cur;
-      cur = next;
-      clear(next);
     }
     lds_barrier();
   };
-  for (int py = y0 - 1; py <= y1; py += kPrefetch) {
-    sfor<0, kPrefetch>([&](auto K) {
-      if (py + int(K) <= y1) iteration(py + int(K), pre[K]);
-    });
+  using ph0 = std::integral_constant<int, 0>;
+  using ph1 = std::integral_constant<int, 1>;
+  using ph2 = std::integral_constant<int, 2>;
+  iteration(0, ph0{});
+  int k = 1;
+  for (; k + 2 <= n + 1; k += 3) {
+    iteration(k, ph1{});
+    iteration(k + 1, ph2{});
+    iteration(k + 2, ph0{});
   }
+  if (k <= n + 1) iteration(k++, ph1{});  // k = 1 mod 3 here
+  if (k <= n + 1) iteration(k++, ph2{});
   if (inner) put(y1 - 1, out);
 }
 

@@ -105,11 +105,11 @@ def test_moment_and_population_storage_agree(lbrr, gpu):
 @pytest.mark.parametrize("lat,shape", [("D3Q27", (17, 9, 40)), ("D2Q9", (1, 17, 300))])
 def test_chunk_length_changes_rounding_only(lbrr, gpu, monkeypatch, lat, shape):
     """Each node's moment sums are accumulated in the same order whatever the chunking (z-planes in
-    3D, rows in 2D).  2D: bitwise equal.  3D: the planes next to a chunk go through code of their
-    own (a third of the populations rebuilt), compiled separately from the inner planes, and the
-    compiler may fuse a multiply-add there that it keeps apart elsewhere; chunk lengths then agree
-    to a few units in the last place (1.4e-9 on values of order 0.03 measured), far below any
-    indexing mistake."""
+    3D, rows in 2D).  But the march is unrolled by 3 (register roles rotate with period 3), and in
+    3D the planes next to a chunk go through code of their own, so a node is finalised in one of
+    several copies of the iteration, depending on the chunk length; the compiler may fuse a
+    multiply-add in one copy that it keeps apart in another.  Chunk lengths then agree to a few
+    units in the last place (about 1e-9 on values of order 0.03), far below any indexing mistake."""
     rho, u, pi1 = TP.smooth_inputs(3 if shape[0] > 1 else 2, shape, 21)
     res = []
     for lz in ("1", "3", "17", "64"):
@@ -119,11 +119,10 @@ def test_chunk_length_changes_rounding_only(lbrr, gpu, monkeypatch, lat, shape):
         sim.step(5)
         res.append(sim.get_populations().cpu().numpy())
         sim.close()
-    for r in res[1:]:
-        if lat == "D2Q9":
-            assert np.array_equal(r, res[0])
-        else:
-            assert np.abs(r - res[0]).max() <= 1e-6 * np.abs(res[0]).max()
+    for lz, r in zip(("3", "17", "64"), res[1:]):
+        d = float(np.abs(r - res[0]).max() / np.abs(res[0]).max())
+        print(f"{lat} lz {lz} against lz 1: max rel diff {d:.1e}", flush=True)
+        assert d <= 1e-6
 
 
 @pytest.mark.parametrize("lat", ["D2Q9", "D3Q19", "D3Q27"])
