@@ -58,10 +58,11 @@ size_t elem_size(int storage) {
 //     D3Q27 FP32 256^3 37.1 / 38.6 / 39.9 / 39.2 / 39.6
 //                384^3 38.5 / 39.9 / 41.8 / 39.5 / 37.2
 //                512^3 40.5 / 41.9 / 42.6 / 37.7 / 36.9
-//     D3Q19 order 3 FP32 (lz = 4 / 6 / 9): 256^3 41.1 / 42.0 / 40.5,
-//                384^3 41.4 / 42.4 / 38.3, 512^3 44.6 / 37.9 / 36.2
+//     D3Q19 order 3 FP32 (lz = 3 / 4 / 5 / 6): 256^3 39.2 / 41.1 / 41.8 / 41.9,
+//                384^3 40.0 / 41.4 / 42.6 / 42.4, 448^3 39.7 / 38.4 / 36.5 / 35.3,
+//                512^3 43.0 / 44.5 / 40.9 / 38.0
 //     D3Q27 FP64 (lz = 3 / 4 / 6): 256^3 20.8 / 21.4 / 22.0, 512^3 19.8 / 20.3 / 21.7
-//   So lz = 6, except D3Q19 on planes of 512^2 nodes and more: 4.
+//   So lz = 6, except D3Q19 on planes of 448^2 nodes and more: 4.
 // LBRR_MOM_LZ overrides the choice.
 int moment_lz(int nvalues, int q, int64_t plane_nodes) {
   if (const char* e = std::getenv("LBRR_MOM_LZ")) {
@@ -69,7 +70,7 @@ int moment_lz(int nvalues, int q, int64_t plane_nodes) {
     if (v >= 1) return v;
   }
   if (nvalues == 6) return 4;
-  if (q == 19 && plane_nodes >= 512 * 512) return 4;
+  if (q == 19 && plane_nodes >= 448 * 448) return 4;
   return 6;
 }
 

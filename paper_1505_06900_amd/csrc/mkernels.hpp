@@ -18,15 +18,17 @@
 //
 // Step kernel (3D): a block rebuilds the populations of an MX x TY patch of
 // nodes of one z-plane (64 x 8 in FP32, 32 x 8 in FP64: 55 KiB of LDS),
-// exchanges them through LDS, and the inner (MX-2) x (TY-2) nodes pull theirs.  The block marches along z through a chunk of
-// planes: the populations rebuilt on plane p with c_z = -1, 0, +1 arrive on
-// planes p-1, p, p+1, so each inner thread keeps running moment sums for
-// three target planes, and plane p-1 is complete once plane p has been
-// rebuilt.  A chunk of lz target planes rebuilds lz + 2 planes; a patch
-// rebuilds its one-node halo ring as well.  The halo and chunk overlaps are
-// the price of the 2.7x smaller state: the kernel is bound by the rebuild
-// arithmetic, not by HBM.  The 2D step (k_mstep2) does the same one
-// dimension lower: a row of kRowX nodes marching along y.
+// exchanges them through LDS, and the inner (MX-2) x (TY-2) nodes pull
+// theirs.  The block marches along z through a chunk of planes: the
+// populations rebuilt on plane p with c_z = -1, 0, +1 arrive on planes p-1,
+// p, p+1, so each inner thread keeps running moment sums for three target
+// planes, and plane p-1 is complete once plane p has been rebuilt.  A chunk of
+// lz target planes rebuilds lz + 2 planes; a patch rebuilds its one-node halo
+// ring as well.  The halo and chunk overlaps are the price of the 2.7x smaller
+// state: about 2 rebuilds per node update and about twice the algorithmic
+// bytes read, so the kernel is held by the rebuild arithmetic and by that
+// traffic together, not by the stored bytes.  The 2D step (k_mstep2) does the
+// same one dimension lower: a row of kRowX nodes marching along y.
 #pragma once
 
 #include <hip/hip_runtime.h>
