@@ -268,11 +268,19 @@ __device__ __forceinline__ void coefficients(const Hydro<R>& h, R omega1, R (&C)
 __device__ __forceinline__ float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// The collision conserves mass and momentum (Sec. 2), and the weighted form
+// keeps that in any precision: g(0) is formed first and the outer values share
+// what is left of C0, g(+-1) = (C0 - g(0))/2 +- C1/2.  Then g(-1) + g(0) + g(+1)
+// returns C0 and g(+1) - g(-1) returns C1 up to the round-to-nearest errors of
+// the operations alone.  With the sum 1/6 C0 + 1/2 C2 written out instead, the
+// rounded constants give 2 fl(1/6) + fl(2/3) = 1 + 2^-25 in FP32, so that every
+// weighted transform would scale the zeroth moment of its input by that
+// factor: a systematic growth of the momentum of 2^-24 per step in 3D.
 template <bool Weighted, bool Has1, bool Has2, class R>
 __device__ __forceinline__ void axis3(R c0, R c1, R c2, R& gm, R& g0, R& gp) {
   if constexpr (Weighted) {
-    R t = R(1.0 / 6.0) * c0;
-    if constexpr (Has2) t = fused(R(0.5), c2, t);
+    g0 = Has2 ? fused(R(2.0 / 3.0), c0, -c2) : R(2.0 / 3.0) * c0;
+    const R t = R(0.5) * (c0 - g0);
     if constexpr (Has1) {
       gm = fused(R(-0.5), c1, t);
       gp = fused(R(0.5), c1, t);
@@ -280,7 +288,6 @@ __device__ __forceinline__ void axis3(R c0, R c1, R c2, R& gm, R& g0, R& gp) {
       gm = t;
       gp = t;
     }
-    g0 = Has2 ? fused(R(2.0 / 3.0), c0, -c2) : R(2.0 / 3.0) * c0;
   } else {
     R t = c0;
     if constexpr (Has2) t = fused(R(2.0 / 3.0), c2, c0);
@@ -292,6 +299,24 @@ __device__ __forceinline__ void axis3(R c0, R c1, R c2, R& gm, R& g0, R& gp) {
       gp = t;
     }
     g0 = Has2 ? fused(R(-1.0 / 3.0), c2, c0) : c0;
+  }
+}
+
+// w_i v for a lattice whose weights are not dyadic (D3Q19: 1/3, 1/18, 1/36).
+// In FP32 the weight is split into its rounded value and the remainder, so the
+// product carries one rounding of the exact w_i v: a plainly rounded weight
+// would scale every population of its class by the same factor at every step
+// (fl(1/18) = (1 + 7.5e-9)/18), a drift of mass and momentum.  In FP64 that
+// factor is below 1e-16 and the weight is used as rounded.
+template <class L, int I, class R>
+__device__ __forceinline__ R times_weight(R v) {
+  constexpr double w = L::w(I);
+  if constexpr (std::is_same_v<R, float>) {
+    constexpr float hi = float(w);
+    constexpr float lo = float(w - double(hi));
+    return fused(hi, v, lo * v);
+  } else {
+    return R(w) * v;
   }
 }
 
@@ -350,7 +375,10 @@ struct GramD3Q19 {
     for (int r = 0; r < K; ++r)
       for (int s = 0; s < K; ++s) {
         double v = g[r][K + s];
-        if (v < 1e-12 && v > -1e-12) v = 0.0;  // exact zeros of the sparse inverse
+        // integers exactly (the rows of the zeroth and first moments are 1 and
+        // 3 times the identity), zeros of the sparse inverse exactly
+        const double n = double(static_cast<long long>(v < 0 ? v - 0.5 : v + 0.5));
+        if (v - n < 1e-12 && v - n > -1e-12) v = n;
         inv[ks[r]][ks[s]] = v;
       }
   }
@@ -361,13 +389,90 @@ struct GramD3Q19Table {
   static constexpr GramD3Q19<N> t{};
 };
 
+// D3Q19 in FP32: the reconstruction does not keep the zeroth and first
+// moments exactly.  The constants 2/3 and 1/3 of its plain transforms are
+// rounded, which shifts the fractional bits of every rounding that follows
+// the same way, and mass and momentum drift by about 1e-11 per node and step.
+// The weights are not products, so no per-axis form holds them by
+// construction as in the weighted transform.  Instead the populations are
+// made to carry the node's own moments, which the collision conserves
+// (Sec. 2):
+//  * z momentum: the faces (0, 0, +-1) take the part of j_z the other
+//    populations of the c_z = +-1 layers lack, half each, keeping their sum;
+//  * x and y momentum: the same with the faces (+-1, 0, 0) and (0, +-1, 0);
+//  * mass: the rest population is drho minus the sum of the other 18.
+// Each is one rounding of a plain sum, with no constant in it.  Only the
+// c_z = +-1 layers enter the z step and only layer c_z = 0 is changed after
+// it.  A layer-selected rebuild (ZSel = +-1) therefore computes both c_z = +-1
+// layers and gets the same bits for them as a full one.
+// Lattice index of velocity (cx, cy, cz) (-1 if the lattice lacks it).
+template <class L>
+constexpr int velocity_index(int cx, int cy, int cz) {
+  for (int i = 0; i < L::Q; ++i)
+    if (L::cx(i) == cx && L::cy(i) == cy && L::cz(i) == cz) return i;
+  return -1;
+}
+
+template <class L, class R>
+__device__ __forceinline__ void conserve_layers(const R (&C)[3][3][3], R* out) {
+  constexpr int zp = velocity_index<L>(0, 0, 1), zm = velocity_index<L>(0, 0, -1);
+  R e = R(-0.0);  // z momentum of the c_z = +-1 populations other than the two faces
+  sfor<0, L::Q>([&](auto I) {
+    if constexpr (I != zp && I != zm) {
+      if constexpr (L::cz(I) == 1) e = e + out[I];
+      if constexpr (L::cz(I) == -1) e = e - out[I];
+    }
+  });
+  const R s = out[zp] + out[zm];
+  const R d = C[0][0][1] - e;  // what the faces must carry: out[zp] - out[zm]
+  out[zp] = R(0.5) * (s + d);
+  out[zm] = R(0.5) * (s - d);
+}
+
+template <class L, class R>
+__device__ __forceinline__ void conserve_plane(const R (&C)[3][3][3], R* out) {
+  constexpr int xp = velocity_index<L>(1, 0, 0), xm = velocity_index<L>(-1, 0, 0);
+  constexpr int yp = velocity_index<L>(0, 1, 0), ym = velocity_index<L>(0, -1, 0);
+  constexpr int rest = velocity_index<L>(0, 0, 0);
+  R ex = R(-0.0), ey = R(-0.0);
+  sfor<0, L::Q>([&](auto I) {
+    if constexpr (I != xp && I != xm) {
+      if constexpr (L::cx(I) == 1) ex = ex + out[I];
+      if constexpr (L::cx(I) == -1) ex = ex - out[I];
+    }
+    if constexpr (I != yp && I != ym) {
+      if constexpr (L::cy(I) == 1) ey = ey + out[I];
+      if constexpr (L::cy(I) == -1) ey = ey - out[I];
+    }
+  });
+  const R sx = out[xp] + out[xm], dx = C[1][0][0] - ex;
+  out[xp] = R(0.5) * (sx + dx);
+  out[xm] = R(0.5) * (sx - dx);
+  const R sy = out[yp] + out[ym], dy = C[0][1][0] - ey;
+  out[yp] = R(0.5) * (sy + dy);
+  out[ym] = R(0.5) * (sy - dy);
+  R m = R(-0.0);
+  sfor<0, L::Q>([&](auto I) {
+    if constexpr (I != rest) m = m + out[I];
+  });
+  out[rest] = C[0][0][0] - m;
+}
+
+// Layer c_z = z - 1 is computed by a reconstruction with layer selection ZSel.
+template <bool Conserve, int ZSel>
+constexpr bool layer_needed(int z) {
+  return ZSel == 2 || z == ZSel + 1 || (Conserve && z != 1);
+}
+
 // Post-collision deviations of the lattice's q populations from C.  With
-// ZSel = -1 or +1 (3D) only the populations with c_z = ZSel are written (the
-// other entries of out are left untouched); ZSel = 2 writes all q.
+// ZSel = -1 or +1 (3D) the populations with c_z = ZSel are written (D3Q19 in
+// FP32 writes both c_z = +-1 layers, see conserve_layers; other entries of
+// out are left untouched); ZSel = 2 writes all q.
 template <class L, int N, class R, int ZSel = 2>
 __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
   static_assert(ZSel == 2 || (L::D == 3 && (ZSel == -1 || ZSel == 1)), "layer selection is 3D only");
   constexpr bool W = L::kProduct;
+  constexpr bool kConserve = !W && std::is_same_v<R, float>;
   R B[3][3][3];
   if constexpr (W) {
     sfor<0, 27>([&](auto P) {
@@ -414,7 +519,7 @@ __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
   sfor<0, 3>([&](auto A) {
     sfor<0, NZ>([&](auto Z) {
       constexpr int a = A;
-      if constexpr (kept<L, N>(a, 0, 0) && (ZSel == 2 || int(Z) == ZSel + 1)) {
+      if constexpr (kept<L, N>(a, 0, 0) && layer_needed<kConserve, ZSel>(int(Z))) {
         constexpr bool h1 = kept<L, N>(a, 1, 0), h2 = kept<L, N>(a, 2, 0);
         axis3<W, h1, h2>(G1[a][0][Z], h1 ? G1[a][1][Z] : R(0), h2 ? G1[a][2][Z] : R(0),
                          G2[a][0][Z], G2[a][1][Z], G2[a][2][Z]);
@@ -423,18 +528,22 @@ __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
   });
   // stage x: G2[*][cy][cz] -> populations; D3Q19 multiplies by w_i and skips corners
   sfor<0, NZ>([&](auto Z) {
-    if constexpr (ZSel == 2 || int(Z) == ZSel + 1) sfor<0, 3>([&](auto Y) {
+    if constexpr (layer_needed<kConserve, ZSel>(int(Z))) sfor<0, 3>([&](auto Y) {
       R gm, g0, gp;
       axis3<W, true, true>(G2[0][Y][Z], G2[1][Y][Z], G2[2][Y][Z], gm, g0, gp);
       sfor<0, L::Q>([&](auto I) {
         if constexpr (L::cy(I) + 1 == Y && L::cz(I) + 1 == (L::D == 3 ? int(Z) : 1)) {
           const R v = (L::cx(I) == -1) ? gm : ((L::cx(I) == 0) ? g0 : gp);
           if constexpr (W) out[I] = v;
-          else out[I] = R(L::w(I)) * v;
+          else out[I] = times_weight<L, int(I)>(v);
         }
       });
     });
   });
+  if constexpr (kConserve) {
+    conserve_layers<L>(C, out);
+    if constexpr (ZSel == 2) conserve_plane<L>(C, out);
+  }
 }
 
 // In-place collision of one node's deviations.

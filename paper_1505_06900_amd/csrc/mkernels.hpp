@@ -129,14 +129,6 @@ constexpr bool has_velocity(int cx, int cy, int cz) {
   return true;
 }
 
-// Lattice index of velocity (cx, cy, cz) (must exist).
-template <class L>
-constexpr int velocity_index(int cx, int cy, int cz) {
-  for (int i = 0; i < L::Q; ++i)
-    if (L::cx(i) == cx && L::cy(i) == cy && L::cz(i) == cz) return i;
-  return -1;
-}
-
 // Add the populations of the layer c_z = CZ that arrive at inner node (tx, ty)
 // to its moment sums s: population (cx, cy, CZ) comes from patch node
 // (tx - cx, ty - cy).  Sums along x, then y, then the c_z factors.

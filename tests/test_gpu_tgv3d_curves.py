@@ -2,11 +2,19 @@
 enstrophy curves of the GPU runs against the FP64 oracle's curves over 2500 steps.
 
 The oracle curves are stored in tests/golden/tgv3d_64_<case>_curves.txt, written by
-tests/golden/make_tgv3d_curves.py (oracle only).  Bars (largest relative deviation
-over the curve): FP64 storage 1e-9; FP32 5e-4, from the rounding drift of the
-stored FP32 state (velocity error growing by about 6e-8 per step, so about
-1.5e-4 after 2500 steps and twice that in the quadratic kinetic energy);
-FP16 2e-2; the enstrophy, a derivative quantity, gets 5 times the bar.
+tests/golden/make_tgv3d_curves.py (oracle only).  Bars (largest relative deviation over
+the curve, kinetic energy / enstrophy):
+* FP64 storages 1e-9 / 5e-9;
+* FP32 storages at Ma 0.1 2e-6 / 1e-5: the collision conserves mass and momentum in FP32
+  arithmetic, so the stored state departs from FP64 only by unbiased rounding (measured
+  3e-7 / 8e-7);
+* FP32 storages at Ma 0.5 5e-5 / 1.5e-4: the flow is turbulent by the end (the kinetic
+  energy falls to 1.2% of its start), which amplifies the rounding (measured 1e-5 / 3e-5);
+* FP16 at Ma 0.1 1e-3 / 2e-3 (measured 2.6e-4 / 5.2e-4);
+* FP16 at Ma 0.5: half-precision rounding decorrelates the turbulent flow completely, so the
+  run is another realization of it.  Its bar is twice the largest deviation of FP64 runs
+  whose initial velocity carries random relative noise of FP16's rounding size (2^-12),
+  measured in the same test.
 """
 import os
 
@@ -17,7 +25,12 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-TOL = {"fp64": 1e-9, "fp32": 5e-4, "fp16": 2e-2, "mom_fp64": 1e-9, "mom_fp32": 5e-4}
+TOL = {  # (case, storage) -> (kinetic energy, enstrophy)
+    "fp64": (1e-9, 5e-9), "mom_fp64": (1e-9, 5e-9),
+    ("ma01", "fp32"): (2e-6, 1e-5), ("ma01", "mom_fp32"): (2e-6, 1e-5),
+    ("ma05", "fp32"): (5e-5, 1.5e-4), ("ma05", "mom_fp32"): (5e-5, 1.5e-4),
+    ("ma01", "fp16"): (1e-3, 2e-3),
+}
 
 
 def load(case):
@@ -25,14 +38,9 @@ def load(case):
     return d[:, 0].astype(int), d[:, 1], d[:, 2]
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "mom_fp64", "mom_fp32"])
-@pytest.mark.parametrize("case", ["ma01", "ma05"])
-def test_tgv3d_curves_match_oracle(lbrr, gpu, case, storage):
-    cfg = W.WORKLOADS[f"tgv3d_64_{case}"]
+def curves(P, cfg, storage, steps, rho, u):
     n = cfg["n"]
-    steps, ke_ref, ens_ref = load(case)
-    rho, u = W.tgv3d(n, cfg["u0"])
-    sim = lbrr.Simulation("D3Q27", (n, n, n), cfg["tau"], cfg["order"], storage=storage)
+    sim = P.Simulation("D3Q27", (n, n, n), cfg["tau"], cfg["order"], storage=storage)
     sim.init_fields(rho, u)
     ke, ens = [], []
     for t in steps:
@@ -40,9 +48,34 @@ def test_tgv3d_curves_match_oracle(lbrr, gpu, case, storage):
         ke.append(sim.reduce()[4] / n**3)
         ens.append(sim.enstrophy())
     sim.close()
-    e_ke = np.max(np.abs(np.array(ke) - ke_ref) / ke_ref)
-    e_en = np.max(np.abs(np.array(ens) - ens_ref) / ens_ref)
+    return np.array(ke), np.array(ens)
+
+
+def deviation(ke, ens, ke_ref, ens_ref):
+    return float(np.max(np.abs(ke - ke_ref) / ke_ref)), float(np.max(np.abs(ens - ens_ref) / ens_ref))
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "mom_fp64", "mom_fp32"])
+@pytest.mark.parametrize("case", ["ma01", "ma05"])
+def test_tgv3d_curves_match_oracle(lbrr, gpu, case, storage):
+    cfg = W.WORKLOADS[f"tgv3d_64_{case}"]
+    steps, ke_ref, ens_ref = load(case)
+    rho, u = W.tgv3d(cfg["n"], cfg["u0"])
+    ke, ens = curves(lbrr, cfg, storage, steps, rho, u)
+    e_ke, e_en = deviation(ke, ens, ke_ref, ens_ref)
     print(f"TGV3D {case} {storage}: max rel dev KE {e_ke:.2e} enstrophy {e_en:.2e}; "
           f"KE(end)/KE(0) {ke[-1] / ke[0]:.5f}, enstrophy peak at step {steps[int(np.argmax(ens))]}", flush=True)
-    assert e_ke <= TOL[storage]
-    assert e_en <= 5 * TOL[storage]
+    if (case, storage) == ("ma05", "fp16"):
+        spread = []
+        rng = np.random.default_rng(7)
+        for _ in range(3):
+            u_n = u * (1.0 + 2.0**-12 * rng.standard_normal(u.shape))
+            spread.append(deviation(*curves(lbrr, cfg, "fp64", steps, rho, u_n), ke_ref, ens_ref))
+        s_ke, s_en = (max(s[k] for s in spread) for k in (0, 1))
+        print(f"  FP64 runs with 2^-12 relative noise on u: max rel dev KE {s_ke:.2e} enstrophy {s_en:.2e}",
+              flush=True)
+        bar = (2 * s_ke, 2 * s_en)
+    else:
+        bar = TOL.get(storage) or TOL[(case, storage)]
+    assert e_ke <= bar[0]
+    assert e_en <= bar[1]
