@@ -10,9 +10,11 @@ import numpy as np
 import pytest
 
 import test_oracle_collision as TC
+import test_oracle_diagnostics as TD
 import test_oracle_lattice as TL
 import test_oracle_lsa as TS
 import test_oracle_physics as TP
+from oracle import diagnostics as OD
 from oracle import rr
 
 CS2 = 1.0 / 3.0
@@ -172,5 +174,96 @@ def test_planted_mistake_is_caught(name, monkeypatch):
     monkeypatch.setattr(rr, "_orig_moments", rr.moments, raising=False)
     monkeypatch.setattr(rr, attr, bad)
     failed = _quick_pins()
+    print(name, "->", failed)
+    assert failed, f"no pin caught: {name}"
+
+
+# ---- diagnostics (Sec. 4.1 energy and enstrophy) ------------------------------
+
+def _diag_pins():
+    checks = {
+        "fourier mode 3D": TD.test_vorticity_of_a_fourier_mode_3d,
+        "fourier mode 2D": TD.test_vorticity_of_a_fourier_mode_2d,
+        "mode enstrophy": TD.test_enstrophy_of_a_fourier_mode,
+        "TGV enstrophy": lambda: TD.test_taylor_green_enstrophy_at_t0(16),
+        "uniform totals": TD.test_totals_of_a_uniform_flow,
+        "density wave": TD.test_totals_of_a_density_wave,
+        "TGV energy": lambda: TD.test_taylor_green_energy_at_t0(8),
+    }
+    failed = []
+    for name, fn in checks.items():
+        try:
+            fn()
+        except (AssertionError, ValueError, IndexError):
+            failed.append(name)
+    return failed
+
+
+def _vorticity_swapped_axis(u):
+    X, Y, Z = 2, 1, 0
+    if u.shape[0] == 2:
+        return (OD._ddx(u[1], X) - OD._ddx(u[0], Y))[None]
+    ux, uy, uz = u
+    # planted: d(u_z)/dx in place of d(u_z)/dy in the x component
+    return np.stack([OD._ddx(uz, X) - OD._ddx(uy, Z), OD._ddx(ux, Z) - OD._ddx(uz, X), OD._ddx(uy, X) - OD._ddx(ux, Y)])
+
+
+def _vorticity_flipped_z(u):
+    X, Y, Z = 2, 1, 0
+    if u.shape[0] == 2:
+        return (OD._ddx(u[0], Y) - OD._ddx(u[1], X))[None]  # planted: sign of w_z
+    ux, uy, uz = u
+    return np.stack([OD._ddx(uz, Y) - OD._ddx(uy, Z), OD._ddx(ux, Z) - OD._ddx(uz, X), OD._ddx(ux, Y) - OD._ddx(uy, X)])
+
+
+def _ddx_one_sided(a, axis):
+    return np.roll(a, -1, axis=axis) - a  # planted: forward difference in place of the central one
+
+
+def _enstrophy_without_half(u):
+    w = OD.vorticity(u)
+    return float(np.mean(np.sum(w * w, axis=0)))
+
+
+def _totals_without_rho_in_energy(rho, u):
+    mom = [float(np.sum(rho * u[d])) for d in range(u.shape[0])]
+    while len(mom) < 3:
+        mom.append(0.0)
+    ke = float(np.sum(0.5 * np.sum(u * u, axis=0)))  # planted: rho dropped from the energy
+    return (float(np.sum(rho)), mom[0], mom[1], mom[2], ke)
+
+
+def _totals_velocity_as_momentum(rho, u):
+    mom = [float(np.sum(u[d])) for d in range(u.shape[0])]  # planted: sum of u, not of rho u
+    while len(mom) < 3:
+        mom.append(0.0)
+    ke = float(np.sum(0.5 * rho * np.sum(u * u, axis=0)))
+    return (float(np.sum(rho)), mom[0], mom[1], mom[2], ke)
+
+
+def _ke_mean_without_half(rho, u):
+    return float(np.mean(rho * np.sum(u * u, axis=0)))
+
+
+DIAG_MUTATIONS = {
+    "vorticity with a swapped derivative axis": ("vorticity", _vorticity_swapped_axis),
+    "vorticity with the sign of w_z flipped": ("vorticity", _vorticity_flipped_z),
+    "one-sided difference": ("_ddx", _ddx_one_sided),
+    "enstrophy without the 1/2": ("enstrophy", _enstrophy_without_half),
+    "energy without rho": ("totals", _totals_without_rho_in_energy),
+    "momentum without rho": ("totals", _totals_velocity_as_momentum),
+    "mean energy without the 1/2": ("kinetic_energy_mean", _ke_mean_without_half),
+}
+
+
+def test_unmutated_diagnostics_pass_their_pins():
+    assert _diag_pins() == []
+
+
+@pytest.mark.parametrize("name", list(DIAG_MUTATIONS))
+def test_planted_diagnostics_mistake_is_caught(name, monkeypatch):
+    attr, bad = DIAG_MUTATIONS[name]
+    monkeypatch.setattr(OD, attr, bad)
+    failed = _diag_pins()
     print(name, "->", failed)
     assert failed, f"no pin caught: {name}"
