@@ -99,7 +99,9 @@ lb_handle lb_create(int lattice, int nx, int ny, int nz, double tau, int order);
 int lb_config(lb_handle h, int storage, double rho0);
 
 /* Use hip_stream (a hipStream_t, may be NULL for the null stream) for all
- * later device work of this handle. */
+ * later device work of this handle.  Work already enqueued on the previous
+ * stream is ordered before it (the new stream waits for an event recorded on
+ * the old one; the host does not block). */
 int lb_set_stream(lb_handle h, void* hip_stream);
 
 /* Set the state at t = 0 from macroscopic fields.  The pre-collision

@@ -236,8 +236,14 @@ int ensure_buffers(lb_ctx* h) {
   }
   const int64_t nb = (h->nodes() + 2047) / 2048;
   h->nblocks = int(nb < 1 ? 1 : (nb > 2048 ? 2048 : nb));
-  HIP_TRY(hipMalloc(&h->partials, sizeof(double) * 5 * h->nblocks), "hipMalloc partials");
-  HIP_TRY(hipMalloc(&h->dev_out, sizeof(double) * 8), "hipMalloc reduction output");
+  // a failure here frees the population buffers too: buf[0] marks a complete set
+  hipError_t e = hipMalloc(&h->partials, sizeof(double) * 5 * h->nblocks);
+  if (e == hipSuccess) e = hipMalloc(&h->dev_out, sizeof(double) * 8);
+  if (e != hipSuccess) {
+    h->release();
+    (void)hipGetLastError();
+    return fail(LB_ERR_OOM, "hipMalloc of the reduction buffers failed: %s", hipGetErrorString(e));
+  }
   return LB_OK;
 }
 
@@ -327,7 +333,18 @@ int lb_config(lb_handle h, int storage, double rho0) {
 
 int lb_set_stream(lb_handle h, void* hip_stream) {
   if (int r = check_handle(h)) return r;
-  h->stream = static_cast<hipStream_t>(hip_stream);
+  hipStream_t next = static_cast<hipStream_t>(hip_stream);
+  if (next != h->stream && h->buf[0]) {
+    // work already enqueued on the old stream comes first: the new stream
+    // waits for an event recorded behind it (nothing blocks the host)
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate");
+    hipError_t e = hipEventRecord(ev, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(next, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(e, "ordering the new stream after the old one");
+  }
+  h->stream = next;
   return LB_OK;
 }
 
