@@ -155,6 +155,30 @@ int lb_moments(lb_handle h, void* rho, void* u, void* pi1, int dtype, int on_dev
  * any total is not finite.  Synchronises the stream. */
 int lb_reduce(lb_handle h, double out[5]);
 
+/* FP64 totals of a population state held by the caller, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Computes what lb_reduce computes
+ * (out[0] = sum rho, out[1..3] = sum rho u, out[4] = sum rho |u|^2 / 2), with
+ * the same kernels and the same partition into blocks, so the same bits,
+ * but allocates nothing and does not synchronise: the per-block partials
+ * live in a static device array of LB_REDUCE_STATIC_MAX_BLOCKS x 5 doubles
+ * (82 KB per GPU, held until the process ends), and the five totals are
+ * written to device memory on the given stream (the caller checks them for
+ * non-finite values).
+ * lattice: LB_D2Q9 / LB_D3Q19 / LB_D3Q27; storage: LB_STORE_FP64, _FP32 or
+ * _FP16 (moment storages: LB_ERR_UNSUPPORTED); populations: device pointer,
+ * compact SoA [q][nz][ny][nx] of the deviations f_i - w_i rho0 in the storage
+ * type (what lb_get_populations writes); out: device pointer to 5 doubles;
+ * hip_stream: a hipStream_t or NULL.  nx*ny*nz < 2^31 (nz = 1 for D2Q9),
+ * which keeps the partials within the static array; anything else returns
+ * LB_ERR_INVALID_ARG.  All calls on one GPU share its static array: calls
+ * that overlap in time on one GPU (two streams, two threads) race; calls in
+ * one stream are ordered.  No part of the array needs clearing: every call
+ * writes every partial it reads. */
+#define LB_REDUCE_STATIC_MAX_BLOCKS 2048
+int lb_reduce_static(int lattice, int storage, int nx, int ny, int nz, double rho0, const void* populations,
+                     double* out, void* hip_stream);
+
 /* Volume mean of |omega|^2 / 2, omega = curl u by second-order periodic
  * central differences (second-order one-sided on walls, lb_set_walls),
  * accumulated in FP64 (the enstrophy of Sec. 4.1, normalised by the number

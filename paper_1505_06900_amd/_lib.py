@@ -23,6 +23,7 @@ LB_ERR_HIP = -4
 LB_ERR_UNSTABLE = -5
 LB_ERR_STATE = -6
 LB_MLP_NPARAM, LB_MLP_NNORM, LB_MLP_NIN = 6723, 78, 36
+LB_REDUCE_STATIC_MAX_BLOCKS = 2048
 
 # name -> (restype, argtypes), exactly the declarations of include/lbrr.h
 _VP, _I, _D, _LL, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong, ctypes.c_size_t
@@ -36,6 +37,7 @@ SIGNATURES = {
     "lb_set_walls": (_I, [_VP, _I]),
     "lb_moments": (_I, [_VP, _VP, _VP, _VP, _I, _I]),
     "lb_reduce": (_I, [_VP, ctypes.POINTER(_D)]),
+    "lb_reduce_static": (_I, [_I, _I, _I, _I, _I, _D, _VP, _VP, _VP]),
     "lb_enstrophy": (_I, [_VP, ctypes.POINTER(_D)]),
     "lb_get_populations": (_I, [_VP, _VP, _I]),
     "lb_set_populations": (_I, [_VP, _VP, _I]),

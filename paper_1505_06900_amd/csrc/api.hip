@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "closure.hpp"
@@ -84,6 +85,41 @@ size_t plane_pad_bytes(size_t plane_bytes) {
     if (v >= 0) return size_t((v + 255) / 256 * 256);
   }
   return (plane_bytes % 65536 == 0) ? 4352 : 0;
+}
+
+// Scratch of lb_reduce_static: the per-block partial totals (5 doubles per
+// block, at most LB_REDUCE_STATIC_MAX_BLOCKS blocks) and nothing else.  A
+// file-scope device array: every GPU the library runs on holds its own copy
+// (82 KB) until the process ends.  Host code never uses the name `scratch`
+// as an address; it uses the per-device address that hipGetSymbolAddress
+// returns (static_scratch below).
+static __device__ __align__(256) double scratch[5 * LB_REDUCE_STATIC_MAX_BLOCKS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// Address of `scratch` on the current device, looked up once per device.
+int static_scratch(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(LB_ERR_UNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch[dev];
+  return LB_OK;
+}
+
+// Per-block partial count of the totals: one block per 2048 nodes, at most
+// LB_REDUCE_STATIC_MAX_BLOCKS (the handle path and lb_reduce_static use the
+// same partition, so their sums are the same bits).
+int totals_blocks(int64_t nodes) {
+  const int64_t nb = (nodes + 2047) / 2048;
+  return int(nb < 1 ? 1 : (nb > LB_REDUCE_STATIC_MAX_BLOCKS ? LB_REDUCE_STATIC_MAX_BLOCKS : nb));
 }
 
 }  // namespace
@@ -234,8 +270,7 @@ int ensure_buffers(lb_ctx* h) {
       return fail(LB_ERR_OOM, "hipMalloc of %zu bytes for populations failed: %s", total, hipGetErrorString(e));
     }
   }
-  const int64_t nb = (h->nodes() + 2047) / 2048;
-  h->nblocks = int(nb < 1 ? 1 : (nb > 2048 ? 2048 : nb));
+  h->nblocks = totals_blocks(h->nodes());
   // a failure here frees the population buffers too: buf[0] marks a complete set
   hipError_t e = hipMalloc(&h->partials, sizeof(double) * 5 * h->nblocks);
   if (e == hipSuccess) e = hipMalloc(&h->dev_out, sizeof(double) * 8);
@@ -471,6 +506,46 @@ int lb_reduce(lb_handle h, double out[5]) {
   if (!out) return fail(LB_ERR_INVALID_ARG, "out must not be NULL");
   if (!h->ready) return fail(LB_ERR_STATE, "no state");
   return totals(h, out);
+}
+
+int lb_reduce_static(int lattice, int storage, int nx, int ny, int nz, double rho0, const void* populations,
+                     double* out, void* hip_stream) {
+  const LatticeOps* ops = nullptr;
+  switch (lattice) {
+    case LB_D2Q9: ops = &lbrr::ops_d2q9(); break;
+    case LB_D3Q19: ops = &lbrr::ops_d3q19(); break;
+    case LB_D3Q27: ops = &lbrr::ops_d3q27(); break;
+    default: return fail(LB_ERR_INVALID_ARG, "unknown lattice %d", lattice);
+  }
+  if (storage != LB_STORE_FP64 && storage != LB_STORE_FP32 && storage != LB_STORE_FP16)
+    return fail(LB_ERR_UNSUPPORTED, "lb_reduce_static takes population storage (FP64, FP32, FP16), got %d", storage);
+  if (nx < 1 || ny < 1 || nz < 1 || (ops->d == 2 && nz != 1))
+    return fail(LB_ERR_INVALID_ARG, "bad dims %d x %d x %d for this lattice", nx, ny, nz);
+  const int64_t nodes = int64_t(nx) * ny * nz;
+  if (nodes >= (int64_t(1) << 31)) return fail(LB_ERR_INVALID_ARG, "nx*ny*nz must be < 2^31");
+  if (!std::isfinite(rho0) || !(rho0 > 0)) return fail(LB_ERR_INVALID_ARG, "rho0 must be finite and > 0");
+  if (!populations || !out) return fail(LB_ERR_INVALID_ARG, "populations and out must not be NULL");
+  const int nblocks = totals_blocks(nodes);
+  if (nblocks > LB_REDUCE_STATIC_MAX_BLOCKS)
+    return fail(LB_ERR_INVALID_ARG, "%d partial blocks exceed the static scratch (%d)", nblocks,
+                LB_REDUCE_STATIC_MAX_BLOCKS);
+  double* partials = nullptr;
+  if (int r = static_scratch(&partials)) return r;
+  StepArgs a{};
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  a.si = nodes;  // compact [q][nz][ny][nx]
+  a.sy = nx;
+  a.sz = int64_t(nx) * ny;
+  a.rho0 = rho0;
+  a.omega1 = 0.0;
+  a.lz = 1;
+  a.walls = 0;
+  const hipError_t e =
+      ops->totals(storage, populations, partials, nblocks, out, a, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "totals kernel launch");
+  return LB_OK;
 }
 
 int lb_enstrophy(lb_handle h, double* out) {

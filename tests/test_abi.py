@@ -68,3 +68,18 @@ def test_header_enums_match_the_binding(lbrr):
     assert {"LB_STORE_MOM_FP64", "LB_STORE_MOM_FP32", "LB_ERR_UNSUPPORTED"} <= set(vals)
     for k, v in vals.items():
         assert getattr(lbrr, k) == v, k
+
+
+@pytest.mark.parametrize("args,code,msg", [
+    ((7, 1, 8, 8, 1, 1.0), "INVALID_ARG", "unknown lattice"),
+    ((2, 4, 8, 8, 8, 1.0), "UNSUPPORTED", "population storage"),
+    ((0, 1, 8, 8, 2, 1.0), "INVALID_ARG", "dims"),
+    ((2, 1, 2048, 2048, 1024, 1.0), "INVALID_ARG", "2^31"),
+    ((2, 1, 8, 8, 8, 0.0), "INVALID_ARG", "rho0"),
+])
+def test_reduce_static_rejects_bad_arguments_before_any_device_call(lbrr, args, code, msg):
+    import ctypes
+
+    r = lbrr.lb_reduce_static(*args, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
+    assert r == getattr(lbrr, "LB_ERR_" + code)
+    assert msg in lbrr.lb_last_error().decode()
