@@ -7,6 +7,12 @@ its 2D benchmark (Sec. 4.1): the enstrophy is half the integral of the squared
 vorticity.  Here both are reported as volume means (the paper does not
 normalise by the area), vorticity by second-order central differences on the
 periodic lattice, all in FP64.
+
+Pinned by tests/test_oracle_diagnostics.py: the curl of a single Fourier mode
+against its closed form Re(i (sin k) x A e^{ik.x}), the Taylor-Green
+enstrophy and energy at t = 0 in closed form, totals of uniform flows and
+density waves; tests/test_oracle_mutations.py plants mistakes in each
+function and checks that these pins catch them.
 """
 from __future__ import annotations
 

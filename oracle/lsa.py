@@ -11,8 +11,8 @@ mode grows when |lambda| > 1.
 
 Lambda is computed by complex-step differentiation of the oracle collision
 (the collision is a rational function of f, so the complex step is exact to
-rounding); the eigenvalues come from numpy's LAPACK binding, as the paper
-says it used "a linear algebra package".
+rounding); the eigenvalues come from numpy's LAPACK binding (Sec. 3.6
+computes them numerically with a linear-algebra library too).
 """
 from __future__ import annotations
 
