@@ -194,6 +194,49 @@ def copy_probe(P, torch, nbytes=2 << 30, reps=10):
     return {"bytes_moved_per_launch": 2 * nbytes, "ms": round(ms, 4), "gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def probe_table(P, torch, nbytes=2 << 30, reps=10):
+    """HBM rates of plain access patterns (lb_probe_bandwidth) on 2 GiB buffers: copy, read, write
+    and the copy of q equal planes, by bytes per lane, one-shot or persistent grid, plain or
+    non-temporal accesses.  GB/s counts the bytes each launch reads plus those it writes."""
+    import ctypes
+
+    src = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    names = {0: "copy", 1: "read", 2: "write", 3: "stream copy"}
+    configs = []
+    for kind in (0, 1, 2):
+        for vec in (4, 8, 16):
+            for bpc in (0, 2, 4, 8, 16):
+                for nt in (0, 1):
+                    configs.append((kind, vec, bpc, nt, 1))
+    for streams in (1, 2, 4, 9, 18, 27, 32):
+        for vec in (4, 8, 16):
+            for nt in (0, 1):
+                configs.append((3, vec, 0, nt, streams))
+    rows = []
+    for kind, vec, bpc, nt, streams in configs:
+        n = nbytes - nbytes % (16 * streams * vec) if kind == 3 else nbytes
+        args = (kind, vec, bpc, nt, streams, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), n, sp)
+        P.check(P.lb_probe_bandwidth(*args))
+        P.check(P.lb_probe_bandwidth(*args))
+        e0.record(stream)
+        for _ in range(reps):
+            P.check(P.lb_probe_bandwidth(*args))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        moved = n * (2 if kind in (0, 3) else 1)
+        rows.append({"kind": names[kind], "vec_bytes": vec, "blocks_per_cu": bpc, "nontemporal": nt,
+                     "streams": streams, "bytes": moved, "ms": round(ms, 4),
+                     "gbs": round(moved / (ms * 1e-3) / 1e9, 1)})
+        log(f"probe {rows[-1]}")
+    del src, dst
+    return rows
+
+
 def probe(P, torch, storages, steps=5):
     """Short fixed launch sequence for hardware-counter runs: copies of known size, then step kernels."""
     import ctypes
@@ -395,6 +438,7 @@ def main(argv=None):
     ap.add_argument("--storages", default="fp32,fp16,fp64,mom_fp32",
                     help="state storages to time; the first one is the headline value")
     ap.add_argument("--probe", action="store_true", help="short launch sequence for rocprofv3 counter runs")
+    ap.add_argument("--probe-table", action="store_true", help="HBM rates of plain access patterns, then exit")
     ap.add_argument("--summarize-prof", nargs="+", metavar="DIR", help="summarise rocprofv3 CSV output and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM traffic summary of the step kernels from two --pmc runs of --probe")
@@ -423,6 +467,9 @@ def main(argv=None):
 
     if a.probe:
         print(json.dumps(probe(P, torch, a.storages.split(","))), flush=True)
+        return 0
+    if a.probe_table:
+        print(json.dumps(probe_table(P, torch)), flush=True)
         return 0
     cfg = W.WORKLOADS[WORKLOAD]
     n = cfg["n"]

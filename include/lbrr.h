@@ -284,6 +284,18 @@ int lb_mlp_adam(float* params, float* m, float* v, const float* grad, long long 
  * calibration kernel. */
 int lb_probe_copy(const void* src, void* dst, size_t n, void* hip_stream);
 
+/* Bandwidth probes of n bytes on hip_stream (no lattice arithmetic): kind 0
+ * copy src -> dst, 1 read src (dst is written only for values a zero-filled
+ * src cannot give), 2 write dst, 3 copy of `streams` (1..32) equal planes,
+ * each thread copying its element of every plane.  vec_bytes 4, 8 or 16 per
+ * lane; blocks_per_cu 0 = one thread per element, 1..64 = that many
+ * 256-thread blocks per compute unit striding over the buffer (kinds 0-2);
+ * nontemporal != 0 uses non-temporal loads and stores.  16-byte aligned
+ * pointers, n a multiple of 16 (kind 3: of vec_bytes * streams).  They give
+ * the HBM rate simple patterns reach on this GPU, beside the vendor peak. */
+int lb_probe_bandwidth(int kind, int vec_bytes, int blocks_per_cu, int nontemporal, int streams, const void* src,
+                       void* dst, size_t n, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

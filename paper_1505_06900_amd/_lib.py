@@ -46,6 +46,7 @@ SIGNATURES = {
     "lb_destroy": (None, [_VP]),
     "lb_last_error": (ctypes.c_char_p, []),
     "lb_probe_copy": (_I, [_VP, _VP, _SZ, _VP]),
+    "lb_probe_bandwidth": (_I, [_I, _I, _I, _I, _I, _VP, _VP, _SZ, _VP]),
     "lb_set_closure": (_I, [_VP, _VP, _VP, _I]),
     "lb_closure_features": (_I, [_VP, _VP, _D, _VP, _VP]),
     "lb_closure_coarsen": (_I, [_VP, _VP, _VP, _I, _I, _I, _I, _D, _D, _VP, _VP, _VP, _VP]),

@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "liblbrr.so")
 # per-kernel register, scratch, LDS and occupancy figures reported by the compiler
 RESOURCES = os.path.join(PKG, "liblbrr_resources.json")
 
-SOURCES = ["api.hip", "diag.hip", "closure.hip", "kernels_d2q9.hip", "kernels_d3q19.hip", "kernels_d3q27.hip"]
+SOURCES = ["api.hip", "diag.hip", "probe.hip", "closure.hip", "kernels_d2q9.hip", "kernels_d3q19.hip", "kernels_d3q27.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -198,19 +198,32 @@ struct lb_ctx {
 
 namespace {
 
-// Population layout.  Measured on MI355X for the step kernel (HBM GB/s):
-// keeping the q rows of a (y, z) row together ([z][y][q][x], layout 1) beats
-// one plane per population ([q][z][y][x], layout 0) by 3-18% on every lattice,
-// size and precision tried (D3Q27 256^3 and 512^3, D3Q19 512^3, D2Q9 2048^2);
-// keeping the q planes of a z-slab together ([z][q][y][x], layout 2) is best
-// again when one plane is small (<= 256 KiB: 256^2 FP32 / FP16), and worst
-// for larger planes.  LBRR_LAYOUT=0|1|2 overrides the choice.
+// Population layout.  Measured on MI355X for the step kernel (GLUPS, each
+// layout three times in one run, interleaved; runs agree to 1%):
+//   * planes of at most 256 KiB (256^2 FP32, 256^2 / 320^2 FP16): keeping the
+//     q planes of a z-slab together ([z][q][y][x], layout 2) is best
+//     (D3Q27 256^3 FP32 27.5 against 26.7 for layout 1);
+//   * larger planes: the q rows of a (y, z) row together ([z][y][q][x],
+//     layout 1) for FP32 at every size and for the rest up to 448^2 planes
+//     (D3Q27 384^3 FP16 55.3 against 53.1 / 53.0);
+//   * planes of 512^2 nodes and more: FP16 keeps layout 2 (D3Q27 512^3 50.3
+//     against 46.4 for layout 1, D3Q19 78.5 against 70.4) and FP64 one volume
+//     per population ([q][z][y][x], layout 0; D3Q27 12.7 against 11.1,
+//     D3Q19 18.2 against 16.4).
+// LBRR_LAYOUT=0|1|2 overrides the choice.
 int layout_choice(int d, int64_t nx, int64_t ny, size_t es) {
   if (const char* e = std::getenv("LBRR_LAYOUT")) {
     const int v = std::atoi(e);
     if (v >= 0 && v <= 2) return v;
   }
-  return (d == 3 && size_t(nx * ny) * es <= 262144) ? 2 : 1;
+  if (d != 3) return 1;
+  const int64_t plane_nodes = nx * ny;
+  if (size_t(plane_nodes) * es <= 262144) return 2;
+  if (plane_nodes >= 512 * 512) {
+    if (es == 2) return 2;
+    if (es == 8) return 0;
+  }
+  return 1;
 }
 
 // Moment-state layout: the fields of a (y, z) row together ([z][y][c][x],
@@ -770,6 +783,27 @@ int lb_probe_copy(const void* src, void* dst, size_t n, void* hip_stream) {
     return fail(LB_ERR_INVALID_ARG, "copy needs 16-byte aligned pointers and a size multiple of 16");
   hipError_t e = lbrr::launch_copy(src, dst, n, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "copy kernel");
+  return LB_OK;
+}
+
+int lb_probe_bandwidth(int kind, int vec_bytes, int blocks_per_cu, int nontemporal, int streams, const void* src,
+                       void* dst, size_t n, void* hip_stream) {
+  if (kind < 0 || kind > 3) return fail(LB_ERR_INVALID_ARG, "kind must be 0 (copy), 1 (read), 2 (write) or 3 (streams)");
+  if (vec_bytes != 4 && vec_bytes != 8 && vec_bytes != 16) return fail(LB_ERR_INVALID_ARG, "vec_bytes must be 4, 8 or 16");
+  if (blocks_per_cu < 0 || blocks_per_cu > 64) return fail(LB_ERR_INVALID_ARG, "blocks_per_cu must be in [0, 64]");
+  if (kind == 3 && (streams < 1 || streams > 32)) return fail(LB_ERR_INVALID_ARG, "streams must be in [1, 32]");
+  if (kind == 3 && blocks_per_cu != 0) return fail(LB_ERR_INVALID_ARG, "the stream copy launches one thread per element");
+  if (!src || !dst) return fail(LB_ERR_INVALID_ARG, "NULL pointer");
+  if (n % 16 || (reinterpret_cast<uintptr_t>(src) % 16) || (reinterpret_cast<uintptr_t>(dst) % 16))
+    return fail(LB_ERR_INVALID_ARG, "probes need 16-byte aligned pointers and a size multiple of 16");
+  if (kind == 3 && (n / size_t(vec_bytes)) % size_t(streams))
+    return fail(LB_ERR_INVALID_ARG, "the stream copy needs a whole number of elements per stream");
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+  const hipError_t e = lbrr::launch_probe(kind, vec_bytes, blocks_per_cu, nontemporal, streams, src, dst, n, cus,
+                                          static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "probe kernel");
   return LB_OK;
 }
 

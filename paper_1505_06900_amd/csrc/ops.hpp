@@ -50,6 +50,8 @@ const LatticeOps& ops_d3q19();
 const LatticeOps& ops_d3q27();
 
 // diagnostics kernels (diag.hip)
+hipError_t launch_probe(int kind, int vec_bytes, int blocks_per_cu, int nontemporal, int streams, const void* src,
+                        void* dst, size_t nbytes, int cus, hipStream_t s);
 hipError_t launch_enstrophy(const double* u, int d, int nx, int ny, int nz, int walls, double* partials, int nblocks,
                             double* out, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t n, hipStream_t s);
