@@ -181,8 +181,11 @@ int lb_reduce_static(int lattice, int storage, int nx, int ny, int nz, double rh
 
 /* Volume mean of |omega|^2 / 2, omega = curl u by second-order periodic
  * central differences (second-order one-sided on walls, lb_set_walls),
- * accumulated in FP64 (the enstrophy of Sec. 4.1, normalised by the number
- * of nodes).  Synchronises the stream. */
+ * accumulated in FP64: the enstrophy of Sec. 4.1 (half the integral of
+ * omega^2) divided by the volume.  On a walled axis the integral is the
+ * trapezoid rule over the box whose faces are the wall nodes (those nodes
+ * weigh 1/2, and n nodes span n - 1 cells); a periodic axis of n nodes
+ * spans n cells of weight 1.  Synchronises the stream. */
 int lb_enstrophy(lb_handle h, double* out);
 
 /* Copy the stored post-collision deviations f_i - w_i rho0 out of / into the

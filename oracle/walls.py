@@ -127,15 +127,39 @@ def one_sided_derivative(a, axis, walled):
     return d
 
 
+def trapezoid_mean(a, walls):
+    """Mean of a (nz, ny, nx) field over the box by the trapezoid rule on walled axes.
+
+    A walled axis of n nodes has its walls on the first and last node: the box spans n - 1
+    cells along it and those two nodes weigh 1/2.  A periodic axis of n nodes spans n cells of
+    weight 1 (the plain mean)."""
+    X, Y, Z = 2, 1, 0
+    w = np.ones_like(a)
+    vol = 1.0
+    for k, ax in ((0, X), (1, Y), (2, Z)):
+        n = a.shape[ax]
+        if k < len(walls) and walls[k]:
+            wt = np.ones(n)
+            wt[0] = wt[-1] = 0.5
+            shape = [1, 1, 1]
+            shape[ax] = n
+            w = w * wt.reshape(shape)
+            vol *= n - 1
+        else:
+            vol *= n
+    return float(np.sum(w * a) / vol)
+
+
 def enstrophy_walls(u, walls):
-    """Volume mean of |omega|^2 / 2 with one-sided differences on the walls (u: (D, nz, ny, nx))."""
+    """Enstrophy of Sec. 4.1 (half the integral of |omega|^2) over the box, divided by its
+    volume: one-sided differences on the walls, trapezoid rule on walled axes (u: (D, nz, ny, nx))."""
     X, Y, Z = 2, 1, 0
     dd = lambda a, ax, k: one_sided_derivative(a, ax, walls[k])
     if u.shape[0] == 2:
         w = dd(u[1], X, 0) - dd(u[0], Y, 1)
-        return float(np.mean(0.5 * w * w))
+        return trapezoid_mean(0.5 * w * w, walls)
     ux, uy, uz = u
     wx = dd(uz, Y, 1) - dd(uy, Z, 2)
     wy = dd(ux, Z, 2) - dd(uz, X, 0)
     wz = dd(uy, X, 0) - dd(ux, Y, 1)
-    return float(np.mean(0.5 * (wx * wx + wy * wy + wz * wz)))
+    return trapezoid_mean(0.5 * (wx * wx + wy * wy + wz * wz), walls)

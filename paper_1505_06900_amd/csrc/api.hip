@@ -574,7 +574,11 @@ int lb_enstrophy(lb_handle h, double* out) {
   double s = 0.0;
   HIP_TRY(hipMemcpyAsync(&s, h->dev_out, sizeof(double), hipMemcpyDeviceToHost, h->stream), "copy enstrophy");
   HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-  *out = s / double(h->nodes());
+  // trapezoid volume: a walled axis of n nodes spans n - 1 cells, a periodic one n
+  double vol = 1.0;
+  const int dims[3] = {h->nx, h->ny, h->nz};
+  for (int k = 0; k < h->d(); ++k) vol *= double((h->walls >> k & 1) ? dims[k] - 1 : dims[k]);
+  *out = s / vol;
   if (!std::isfinite(*out)) return fail(LB_ERR_UNSTABLE, "non-finite enstrophy");
   return LB_OK;
 }

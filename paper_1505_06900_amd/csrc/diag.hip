@@ -44,6 +44,8 @@ __device__ __forceinline__ double axis_derivative(const double* __restrict__ a, 
 
 // Per-block partial sums of |omega|^2 / 2, omega by second-order differences
 // (periodic, one-sided on the walls of `walls`: bit 0 x, 1 y, 2 z); 2D: w_z.
+// On a walled axis the first and last node carry weight 1/2: the sum is the
+// trapezoid rule of the integral over the box whose faces are the wall nodes.
 __global__ void __launch_bounds__(kReduceBlock) k_enstrophy(const double* __restrict__ u, int d, int nx, int ny,
                                                             int nz, int walls, int64_t per_block,
                                                             double* __restrict__ partials) {
@@ -62,16 +64,18 @@ __global__ void __launch_bounds__(kReduceBlock) k_enstrophy(const double* __rest
     const int z = int(n / sxy);
     const double duy_dx = axis_derivative(uy, n, 1, x, nx, wx);
     const double dux_dy = axis_derivative(ux, n, nx, y, ny, wy);
+    const double wt = ((wx && (x == 0 || x == nx - 1)) ? 0.5 : 1.0) * ((wy && (y == 0 || y == ny - 1)) ? 0.5 : 1.0) *
+                      ((wz && (z == 0 || z == nz - 1)) ? 0.5 : 1.0);
     if (d == 2) {
       const double w = duy_dx - dux_dy;
-      acc += 0.5 * w * w;
+      acc += wt * (0.5 * w * w);
     } else {
       const double duz_dy = axis_derivative(uz, n, nx, y, ny, wy);
       const double duy_dz = axis_derivative(uy, n, sxy, z, nz, wz);
       const double dux_dz = axis_derivative(ux, n, sxy, z, nz, wz);
       const double duz_dx = axis_derivative(uz, n, 1, x, nx, wx);
       const double wxv = duz_dy - duy_dz, wyv = dux_dz - duz_dx, wzv = duy_dx - dux_dy;
-      acc += 0.5 * (wxv * wxv + wyv * wyv + wzv * wzv);
+      acc += wt * (0.5 * (wxv * wxv + wyv * wyv + wzv * wzv));
     }
   }
   block_sum_store1(acc, partials);

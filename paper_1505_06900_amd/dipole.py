@@ -2,8 +2,10 @@
 walls, Re = 2500, run with the library's wall step; the two enstrophy peaks are compared with the
 reference values the paper quotes (3313 and 1418).
 
-Orchestration and measurement only: every step runs in liblbrr.so; torch evaluates the enstrophy
-integral from the velocity field the library returns.
+Orchestration only: the steps, the enstrophy integral (lb_enstrophy, trapezoid rule between the
+walls) and the kinetic energy (lb_reduce) run in liblbrr.so.  Only the largest local speed of the
+constant-Mach runs (their Mach number) is taken with torch from the velocity field lb_moments
+returns.
 
 Scaling (a reading of Sec. 4.1, where the printed rule U_lb = 0.01 N/125 contradicts the stated
 constant viscosity): N nodes per unit length (walls on the first and last of 2N + 1 nodes),
@@ -19,7 +21,7 @@ import time
 
 import numpy as np
 
-from . import Simulation
+from . import LB_ERR_UNSTABLE, LBError, Simulation
 
 RE = 2500.0
 REFERENCE_PEAKS = (3313.0, 1418.0)
@@ -40,49 +42,34 @@ def _torch():
     return torch
 
 
-def enstrophy_integral(u, n_unit, u_lb):
-    """<Omega> = 1/2 int omega^2 dx dy over the box (trapezoid rule), omega by second-order
-    differences (one-sided on the walls), in the paper's units; u (2, 1, m, m) lattice velocity."""
-    torch = _torch()
-    ux, uy = u[0, 0], u[1, 0]
-
-    def d(a, dim):
-        g = torch.empty_like(a)
-        n = a.shape[dim]
-        sl = lambda i, j: a.narrow(dim, i, j)
-        g.narrow(dim, 1, n - 2).copy_(0.5 * (sl(2, n - 2) - sl(0, n - 2)))
-        g.narrow(dim, 0, 1).copy_(0.5 * (-3.0 * sl(0, 1) + 4.0 * sl(1, 1) - sl(2, 1)))
-        g.narrow(dim, n - 1, 1).copy_(0.5 * (3.0 * sl(n - 1, 1) - 4.0 * sl(n - 2, 1) + sl(n - 3, 1)))
-        return g
-
-    w = d(uy, 1) - d(ux, 0)  # lattice vorticity per step
-    m = w.shape[0]
-    wt = torch.ones(m, dtype=w.dtype, device=w.device)
-    wt[0] = wt[-1] = 0.5
-    s = (wt[:, None] * wt[None, :] * w * w).sum()
-    return float(0.5 * s) / (u_lb * u_lb)
+def enstrophy_integral(sim, u_lb):
+    """<Omega> = 1/2 int omega^2 dx dy over the box in the paper's units, from lb_enstrophy: half
+    the trapezoid-rule integral of the lattice vorticity squared (second-order differences,
+    one-sided on the walls) over the (m - 1)^2 cells between the wall nodes, divided by their
+    number; omega is per lattice step, so the paper's vorticity is omega / U_lb in its units."""
+    m = sim.nx
+    return sim.enstrophy() * (m - 1) ** 2 / (u_lb * u_lb)
 
 
-def kinetic_energy(u, u_lb):
-    """1/2 int |u|^2 dx dy (trapezoid), paper's units (rho ~ 1)."""
-    torch = _torch()
-    m = u.shape[-1]
-    n_unit = (m - 1) // 2
-    wt = torch.ones(m, dtype=u.dtype, device=u.device)
-    wt[0] = wt[-1] = 0.5
-    s = (wt[:, None] * wt[None, :] * (u[0, 0] ** 2 + u[1, 0] ** 2)).sum()
-    return float(0.5 * s) / (u_lb * u_lb * n_unit * n_unit)
+def kinetic_energy(sim, u_lb):
+    """1/2 int rho |u|^2 dx dy in the paper's units from lb_reduce (the wall nodes carry u = 0,
+    so the sum over the nodes is the trapezoid rule)."""
+    n_unit = (sim.nx - 1) // 2
+    return sim.reduce()[4] / (u_lb * u_lb * n_unit * n_unit)
 
 
-def run(n_unit, t_end=1.0, dt_sample=0.002, storage="fp64", order=4, log=None, u_lb=None):
+def run(n_unit, t_end=1.0, dt_sample=0.002, storage="fp64", order=4, log=None, u_lb=None, track_mach=None):
     """Evolve the dipole to t_end; returns dict(times, enstrophy, energy, peaks, errors, ...).
 
     u_lb: lattice velocity unit (default 0.01 * 125 / N, the constant-viscosity series); a fixed
     value gives the constant-Mach series (U_lb = 0.032: the Ma 0.7 runs of Sec. 4.1).
-    log: optional callable, given a progress line every 100 samples."""
+    log: optional callable, given a progress line every 100 samples.
+    track_mach: also record the largest |u| of every sample (default: with a fixed u_lb)."""
     import workloads as W
 
     torch = _torch()
+    if track_mach is None:
+        track_mach = u_lb is not None
     u_lb, nu, tau = lattice_parameters(n_unit, u_lb)
     u_phys, _ = W.dipole(n_unit)
     m = 2 * n_unit + 1
@@ -97,15 +84,22 @@ def run(n_unit, t_end=1.0, dt_sample=0.002, storage="fp64", order=4, log=None, u
     t0 = time.perf_counter()
     k = 0
     while True:
-        _, v = sim.moments(torch.float64)
         times.append(k / steps_per_unit)
-        ens.append(enstrophy_integral(v, n_unit, u_lb))
-        ke.append(kinetic_energy(v, u_lb))
-        umax = max(umax, float(torch.sqrt(v[0] ** 2 + v[1] ** 2).max()))
+        try:
+            e_k, k_k = enstrophy_integral(sim, u_lb), kinetic_energy(sim, u_lb)
+        except LBError as e:  # the run lost its finite state
+            if e.code != LB_ERR_UNSTABLE:
+                raise
+            e_k = k_k = float("nan")
+        ens.append(e_k)
+        ke.append(k_k)
+        if not np.isfinite(e_k):
+            break
+        if track_mach:  # the largest local speed, for the Mach number of the constant-Mach runs
+            _, v = sim.moments(torch.float64)
+            umax = max(umax, float(torch.sqrt(v[0] ** 2 + v[1] ** 2).max()))
         if log is not None and len(times) % 100 == 0:
             log(f"dipole N={n_unit} {storage}: t = {times[-1]:.3f}, enstrophy {ens[-1]:.1f}")
-        if not np.isfinite(ens[-1]):
-            break
         if k >= total:
             break
         n = min(every, total - k)

@@ -118,3 +118,32 @@ def test_one_sided_derivative_is_exact_on_quadratics():
     a = (2.0 + 0.5 * x - 0.25 * x * x)[None, None, :]
     d = OW.one_sided_derivative(a, 2, True)
     np.testing.assert_allclose(d[0, 0], 0.5 - 0.5 * x, atol=1e-14)
+
+
+def test_walled_enstrophy_converges_at_second_order_to_the_integral():
+    """Channel profile u_x = sin(pi y), y = j/(ny - 1) in [0, 1] between walls on the first and
+    last node (periodic x): omega = -(pi/(ny - 1)) cos(pi y) per node, so half the integral of
+    omega^2 over the box divided by its volume is pi^2 / (4 (ny - 1)^2).  One-sided wall
+    differences and the trapezoid rule are both second order: the relative error falls about
+    4x per halving of the spacing (a plain mean over the nodes would give first order, 2x)."""
+    def err(ny):
+        y = np.arange(ny) / (ny - 1)
+        ux = np.sin(np.pi * y)[None, :, None] * np.ones((1, ny, 8))
+        u = np.stack([ux, np.zeros_like(ux)])
+        e = OW.enstrophy_walls(u, (False, True))
+        return abs(e * 4 * (ny - 1) ** 2 / np.pi**2 - 1)
+
+    e = [err(n) for n in (33, 65, 129)]
+    assert e[2] < 1e-3
+    for a, b in zip(e, e[1:]):
+        assert 3.3 < a / b < 4.5
+
+
+def test_trapezoid_mean_weights_and_volume():
+    a = np.arange(3 * 4 * 5, dtype=float).reshape(3, 4, 5)
+    assert OW.trapezoid_mean(a, (False, False, False)) == pytest.approx(a.mean(), rel=1e-15)
+    # walled y: rows 0 and 3 weigh 1/2, three cells
+    wy = np.array([0.5, 1, 1, 0.5])[None, :, None]
+    assert OW.trapezoid_mean(a, (False, True, False)) == pytest.approx(float((a * wy).sum()) / (3 * 3 * 5), rel=1e-15)
+    # constant field: the mean is the constant whatever the walls
+    assert OW.trapezoid_mean(np.full((3, 4, 5), 2.5), (True, True, True)) == pytest.approx(2.5, rel=1e-15)
