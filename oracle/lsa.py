@@ -22,8 +22,9 @@ from . import rr
 from .lattice import lattice
 
 
-def jacobian(lat, N, tau, rho, u, h=1e-30):
-    """Lambda = dOmega/df at the equilibrium with density rho and velocity u."""
+def jacobian(lat, N, tau, rho, u, h=1e-30, n1=None):
+    """Lambda = dOmega/df at the equilibrium with density rho and velocity u (f1 at order n1,
+    default ``rr.f1_order``)."""
     L = lattice(lat) if isinstance(lat, str) else lat
     u = np.asarray(u, dtype=float).reshape(L.D)
     fbar = rr.init_populations(L, N, np.array(rho, dtype=float), u)
@@ -32,17 +33,17 @@ def jacobian(lat, N, tau, rho, u, h=1e-30):
     for j in range(q):
         fc = fbar.astype(complex)
         fc[j] += 1j * h
-        J[:, j] = np.imag(rr.collide(L, N, tau, fc)) / h
+        J[:, j] = np.imag(rr.collide(L, N, tau, fc, n1)) / h
     return J
 
 
-def amplification_eigs(lat, N, tau, rho, u, kx, ky, kz=None):
+def amplification_eigs(lat, N, tau, rho, u, kx, ky, kz=None, n1=None):
     """Eigenvalues of A^-1 Lambda for every wavevector of the given grids.
 
     kx, ky (and kz for 3D) are broadcastable arrays; returns (..., q) complex.
     """
     L = lattice(lat) if isinstance(lat, str) else lat
-    J = jacobian(L, N, tau, rho, u)
+    J = jacobian(L, N, tau, rho, u, n1=n1)
     kx, ky = np.broadcast_arrays(np.asarray(kx, float), np.asarray(ky, float))
     kz = np.zeros_like(kx) if kz is None else np.broadcast_to(np.asarray(kz, float), kx.shape)
     c = L.c.astype(float)

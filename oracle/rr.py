@@ -18,7 +18,8 @@ The scheme, in the paper's order:
 5. reconstruction of f0 and f1 on the lattice's Hermite basis truncated at
    order N (Eqs. fzero_d2q9 / fone_d2q9, fzero_d3q27 / fone_d3q27), written
    as the Gram projection f = W H^T G^-1 a (identical to the printed formulas
-   for D2Q9 / D3Q27, whose Gram matrix is diagonal);
+   for D2Q9 / D3Q27, whose Gram matrix is diagonal); on D3Q19 f1 stops at
+   order 3 (``f1_order``);
 6. post-collision populations f0 + (1 - 1/tau) f1 -- Sec. 3.5, Eq.
    discr_bgk_reg, with tau the shifted relaxation time of Sec. 3.4
    (Eq. full_discr_bgk), so nu = c_s^2 (tau - 1/2);
@@ -132,13 +133,29 @@ def reconstruct(lat, N, a):
     return np.tensordot(R, a, axes=(1, 0))
 
 
-def collide(lat, N, tau, f):
-    """Post-collision populations f0 + (1 - 1/tau) f1 (Eq. discr_bgk_reg), per node."""
+def f1_order(lat, N):
+    """Hermite order of the off-equilibrium part f1 when f0 is truncated at order N.
+
+    N on D2Q9 and D3Q27.  D3Q19 has no complete Hermite basis (Sec. 3.2) and the paper
+    leaves its generalisation open (Sec. 5); on it f1 stops at order 3 while f0 keeps
+    order N.  The alternative, an f1 at order 4 carrying the recursion's fourth-order
+    coefficients through the Gram projection, makes the linearised collision grow at
+    rest for tau close to 1/2 (the analysis of Sec. 3.6, ``test_oracle_lsa``); with f1
+    at order 3 the rest state is stable at every tau."""
+    L = _lat(lat)
+    return min(N, 3) if L.name == "D3Q19" else N
+
+
+def collide(lat, N, tau, f, n1=None):
+    """Post-collision populations f0 + (1 - 1/tau) f1 (Eq. discr_bgk_reg), per node.
+
+    f0 is reconstructed at order N, f1 at order n1 (default ``f1_order(lat, N)``)."""
+    n1 = f1_order(lat, N) if n1 is None else n1
     rho, u, Pi = moments(lat, f)
     A = offeq_second(lat, rho, u, Pi)
-    a0 = a0_coefficients(lat, N, rho, u)
-    a1 = a1_coefficients(lat, N, A, u)
-    return reconstruct(lat, N, a0 + (1.0 - 1.0 / tau) * a1)
+    f0 = reconstruct(lat, N, a0_coefficients(lat, N, rho, u))
+    f1 = reconstruct(lat, n1, a1_coefficients(lat, n1, A, u))
+    return f0 + (1.0 - 1.0 / tau) * f1
 
 
 def stream(lat, f):
@@ -150,31 +167,33 @@ def stream(lat, f):
     return out
 
 
-def step(lat, N, tau, f):
+def step(lat, N, tau, f, n1=None):
     """One time step on pre-collision populations (Eq. discr_bgk_reg as printed: collide, then stream)."""
-    return stream(lat, collide(lat, N, tau, f))
+    return stream(lat, collide(lat, N, tau, f, n1))
 
 
-def step_post(lat, N, tau, g):
+def step_post(lat, N, tau, g, n1=None):
     """One time step on post-collision populations: stream, then collide.
 
     A state stored after the collision (g = collide(f)) advances by
     g(t+1) = collide(stream(g(t))); the moments rho, u of g(t) and f(t) agree
     because the collision conserves them.
     """
-    return collide(lat, N, tau, stream(lat, g))
+    return collide(lat, N, tau, stream(lat, g), n1)
 
 
-def init_populations(lat, N, rho, u, pi1=None):
-    """Pre-collision populations f0^(N)(rho, u) [+ f1^(N)(u, a1^(2) = pi1)] at t = 0.
+def init_populations(lat, N, rho, u, pi1=None, n1=None):
+    """Pre-collision populations f0^(N)(rho, u) [+ f1^(n1)(u, a1^(2) = pi1)] at t = 0.
 
     ``pi1`` is a full (3, 3, ...) symmetric tensor or None.  Higher-order
-    off-equilibrium coefficients come from the recursion, as in the collision.
+    off-equilibrium coefficients come from the recursion, as in the collision;
+    n1 defaults to ``f1_order(lat, N)``.
     """
-    a = a0_coefficients(lat, N, rho, u)
+    f = reconstruct(lat, N, a0_coefficients(lat, N, rho, u))
     if pi1 is not None:
-        a = a + a1_coefficients(lat, N, pi1, u)
-    return reconstruct(lat, N, a)
+        n1 = f1_order(lat, N) if n1 is None else n1
+        f = f + reconstruct(lat, n1, a1_coefficients(lat, n1, pi1, u))
+    return f
 
 
 def pi1_from_components(lat, comps):
@@ -196,9 +215,9 @@ def pi1_components(lat, A):
     return np.stack([A[a, b] for (a, b) in pairs])
 
 
-def run(lat, N, tau, rho, u, steps, pi1=None):
+def run(lat, N, tau, rho, u, steps, pi1=None, n1=None):
     """Evolve from fields for ``steps`` steps (push form); returns pre-collision populations."""
-    f = init_populations(lat, N, rho, u, pi1)
+    f = init_populations(lat, N, rho, u, pi1, n1)
     for _ in range(steps):
-        f = step(lat, N, tau, f)
+        f = step(lat, N, tau, f, n1)
     return f

@@ -62,9 +62,10 @@ def unknown_mask(lat, shape, walls):
     return unk
 
 
-def regularize_walls(lat, N, f, walls):
+def regularize_walls(lat, N, f, walls, n1=None):
     """Replace the populations of every wall node of a streamed state f (q, nz, ny, nx) by the
-    regularised no-slip populations f0(rho, 0) + f1(0, a1^(2))."""
+    regularised no-slip populations f0(rho, 0) + f1(0, a1^(2)) (f1 at order n1, default
+    ``rr.f1_order(lat, N)``)."""
     L = _lat(lat)
     unk = unknown_mask(L, f.shape[1:], walls)
     wall = unk.any(axis=0)
@@ -85,24 +86,26 @@ def regularize_walls(lat, N, f, walls):
         A[2, :] = 0.0
         A[:, 2] = 0.0
     zero_u = np.zeros((L.D,) + rho.shape)
-    freg = rr.reconstruct(L, N, rr.a0_coefficients(L, N, rho, zero_u) + rr.a1_coefficients(L, N, A, zero_u))
+    n1 = rr.f1_order(L, N) if n1 is None else n1
+    freg = rr.reconstruct(L, N, rr.a0_coefficients(L, N, rho, zero_u)) + rr.reconstruct(
+        L, n1, rr.a1_coefficients(L, n1, A, zero_u))
     return np.where(wall[None], freg, f)
 
 
-def step_walls(lat, N, tau, f, walls):
+def step_walls(lat, N, tau, f, walls, n1=None):
     """One time step on pre-collision populations with resting walls: collide, stream, regularise
     the wall nodes."""
     L = _lat(lat)
-    return regularize_walls(L, N, rr.stream(L, rr.collide(L, N, tau, f)), walls)
+    return regularize_walls(L, N, rr.stream(L, rr.collide(L, N, tau, f, n1)), walls, n1)
 
 
-def run_walls(lat, N, tau, rho, u, steps, walls, pi1=None):
+def run_walls(lat, N, tau, rho, u, steps, walls, pi1=None, n1=None):
     """Evolve from fields (u = 0 expected on the wall nodes) for ``steps`` steps; returns
     pre-collision populations."""
     L = _lat(lat)
-    f = rr.init_populations(L, N, rho, u, pi1)
+    f = rr.init_populations(L, N, rho, u, pi1, n1)
     for _ in range(steps):
-        f = step_walls(L, N, tau, f, walls)
+        f = step_walls(L, N, tau, f, walls, n1)
     return f
 
 

@@ -21,7 +21,8 @@
 //  * D3Q19 has no orthogonal Hermite basis (Sec. 3.2): its kept polynomials
 //    are those with at least one zero exponent, and the reconstruction solves
 //    with their Gram matrix G_kl = sum_i w_i H_k H_l, computed at compile time,
-//    before the same unweighted per-axis transforms and a final w_i.
+//    before the same unweighted per-axis transforms and a final w_i.  On D3Q19
+//    f1 stops at order 3 (see coefficients).
 // Everything is unrolled at compile time; coefficients beyond order N are
 // never formed.
 #pragma once
@@ -241,12 +242,23 @@ __device__ __forceinline__ void coefficients(const Hydro<R>& h, R omega1, R (&C)
             else e = h.jz * pz[c - 1];
             // a1: pair sum of the recursion
             R s = R(-0.0);
-            if constexpr (a == 2) s = s + sxx * py[b] * pz[c];
-            if constexpr (b == 2) s = s + syy * px[a] * pz[c];
-            if constexpr (c == 2) s = s + szz * px[a] * py[b];
-            if constexpr (a > 0 && b > 0) s = s + R(a * b) * sxy * px[a - 1] * py[b - 1] * pz[c];
-            if constexpr (a > 0 && c > 0) s = s + R(a * c) * sxz * px[a - 1] * py[b] * pz[c - 1];
-            if constexpr (b > 0 && c > 0) s = s + R(b * c) * syz * px[a] * py[b - 1] * pz[c - 1];
+            if constexpr (!L::kProduct && n == 4) {
+              // D3Q19: f1 stops at order 3 while f0 keeps order 4.  The population
+              // vector f1^(3) has, on the fourth-order polynomial H_aabb of D3Q19,
+              // the moment -a1_cc / 6 (c the axis with exponent 0): the weights
+              // couple H_aabb to H_cc only.  With that value in place of the
+              // recursion's a1^(4), the order-4 reconstruction below returns
+              // f0^(4) + omega1 f1^(3).  (An f1 at order 4 through the same
+              // projection makes the rest state grow for tau near 1/2.)
+              s = R(-1.0 / 6.0) * (a == 0 ? sxx : (b == 0 ? syy : szz));
+            } else {
+              if constexpr (a == 2) s = s + sxx * py[b] * pz[c];
+              if constexpr (b == 2) s = s + syy * px[a] * pz[c];
+              if constexpr (c == 2) s = s + szz * px[a] * py[b];
+              if constexpr (a > 0 && b > 0) s = s + R(a * b) * sxy * px[a - 1] * py[b - 1] * pz[c];
+              if constexpr (a > 0 && c > 0) s = s + R(a * c) * sxz * px[a - 1] * py[b] * pz[c - 1];
+              if constexpr (b > 0 && c > 0) s = s + R(b * c) * syz * px[a] * py[b - 1] * pz[c - 1];
+            }
             C[a][b][c] = e + s;
           }
         }

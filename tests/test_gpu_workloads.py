@@ -3,7 +3,7 @@
 * double shear layer, D2Q9 order 4, 2048^2, Re 10^4, 20000 steps: at Ma 0.2 FP32 and FP16
   population storage and FP32 moment storage against the FP64 population run; at Ma 0.5 the
   linear instability of the scheme at the local Mach numbers the flow reaches;
-* random divergence-free field, D3Q19 (order 3) and D3Q27 (order 4), 512^3, rms Ma 0.1, 1000 steps: FP16
+* random divergence-free field, D3Q19 and D3Q27 (order 4), 512^3, rms Ma 0.1, 1000 steps: FP16
   population storage and FP32 moment storage against FP32 population storage (the reference of
   this workload), throughput of each;
 * 3D Taylor-Green vortex, D3Q27 order 4, 256^3, Ma 0.1 and 0.5, Re 1600, 10000 steps: FP32,

@@ -126,28 +126,31 @@ def test_projection_reconstruction_identity(name):
 
 @pytest.mark.parametrize("name,N", [(n, N) for n in Lm.LATTICES for N in range(2, Lm.MAX_ORDER[n] + 1)])
 def test_collision_projects_back_to_coefficients(name, N):
-    """Projecting f_out on every kept H_k returns a0_k + (1-1/tau) a1_k; brute-force solve agrees."""
+    """Projecting f_out on every H_k kept by f1 returns a0_k + (1-1/tau) a1_k, and f_out is the
+    sum of the two minimum-norm (W^-1 metric) solutions of the moment constraints, f0 for a0 at
+    order N and f1 for a1 at order n1 (n1 = N, or 3 on D3Q19), by dense solves."""
     L = Lm.lattice(name)
     tau = 0.73
+    n1 = rr.f1_order(L, N)
     rho = 1 + 0.03 * RNG.standard_normal(5)
     u = 0.1 * RNG.standard_normal((L.D, 5))
     A = rr.pi1_from_components(L, 0.01 * RNG.standard_normal((3 if L.D == 2 else 6, 5)))
     f = rr.init_populations(L, N, rho, u, A)
     g = rr.collide(L, N, tau, f)
-    sel = L.kept(N)
-    Hn = L.H[sel]
     a0 = rr.a0_coefficients(L, N, rho, u)
-    a1 = rr.a1_coefficients(L, N, A, u)
-    np.testing.assert_allclose(Hn @ g, a0 + (1 - 1 / tau) * a1, rtol=1e-12, atol=1e-15)
-    # minimum-norm (in the W^-1 metric) solution of the moment constraints, by a dense solve
-    target = a0 + (1 - 1 / tau) * a1
+    a1 = rr.a1_coefficients(L, n1, A, u)
+    H0, H1 = L.H[L.kept(N)], L.H[L.kept(n1)]
+    a0_low = a0[[L.kept(N).index(r) for r in L.kept(n1)]]
+    np.testing.assert_allclose(H1 @ g, a0_low + (1 - 1 / tau) * a1, rtol=1e-12, atol=1e-15)
     W = np.diag(L.w)
     for n in range(5):
-        lam = np.linalg.solve(Hn @ W @ Hn.T, target[:, n])
-        np.testing.assert_allclose(g[:, n], W @ Hn.T @ lam, rtol=1e-12, atol=1e-15)
-    if len(sel) == L.q:  # complete basis: the constraints alone fix f
+        f0 = W @ H0.T @ np.linalg.solve(H0 @ W @ H0.T, a0[:, n])
+        f1 = W @ H1.T @ np.linalg.solve(H1 @ W @ H1.T, a1[:, n])
+        np.testing.assert_allclose(g[:, n], f0 + (1 - 1 / tau) * f1, rtol=1e-12, atol=1e-15)
+    if len(L.kept(N)) == L.q and n1 == N:  # complete basis: the constraints alone fix f
+        target = a0 + (1 - 1 / tau) * a1
         for n in range(5):
-            np.testing.assert_allclose(g[:, n], np.linalg.solve(Hn, target[:, n]), rtol=1e-11, atol=1e-14)
+            np.testing.assert_allclose(g[:, n], np.linalg.solve(H0, target[:, n]), rtol=1e-11, atol=1e-14)
 
 
 @pytest.mark.parametrize("name,N", [(n, N) for n in Lm.LATTICES for N in range(2, Lm.MAX_ORDER[n] + 1)])
@@ -254,8 +257,10 @@ def test_z_invariant_3d_run_marginalises_to_2d(lat3, N):
     """Summing a z-invariant 3D run over c_z gives the D2Q9 run at the same order.
 
     Exact for D3Q27 (tensor-product lattice, h_1 and h_2 have zero marginal) and
-    for D3Q19 at order 4 (the Gram solve restores the marginals); D3Q19 at order
-    2-3 does not marginalise exactly and is not asserted.
+    for D3Q19 with f0 and f1 both at order 4 (the Gram solve restores the
+    marginals: this pins the Gram projection of the fourth-order D3Q19 basis).  The
+    D3Q19 model used elsewhere stops f1 at order 3 (rr.f1_order), and D3Q19 at
+    order 2-3 does not marginalise exactly; those are not asserted.
     """
     n, nz = 8, 3
     rho, u = W.tgv2d(n, 0.06)
@@ -265,10 +270,10 @@ def test_z_invariant_3d_run_marginalises_to_2d(lat3, N):
     u3 = np.concatenate([np.repeat(u, nz, 1), np.zeros((1, nz, n, n))])
     pi3 = np.zeros((3, 3, nz, n, n))
     pi3[:2, :2] = np.repeat(pi[:2, :2], nz, 2)
-    f3 = rr.init_populations(lat3, N, rho3, u3, pi3)
+    f3 = rr.init_populations(lat3, N, rho3, u3, pi3, n1=N)
     for _ in range(6):
         f2 = rr.step("D2Q9", N, 0.7, f2)
-        f3 = rr.step(lat3, N, 0.7, f3)
+        f3 = rr.step(lat3, N, 0.7, f3, n1=N)
     L3, L2 = Lm.lattice(lat3), Lm.lattice("D2Q9")
     F = np.zeros_like(f2)
     for i, c in enumerate(L3.c):

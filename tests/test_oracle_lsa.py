@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import lsa
+from oracle import rr
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "stability.txt")
 TOL = 1e-10  # |lambda| = 1 modes (conserved quantities at k = 0) carry rounding
@@ -73,25 +74,43 @@ def test_dissipation_of_shear_mode_matches_navier_stokes_at_small_k():
     np.testing.assert_allclose(hydro, -nu * k * k, rtol=2e-3)
 
 
-def _max_growth_3d(lat, N, tau, u, nk=16):
+def _max_growth_3d(lat, N, tau, u, nk=16, n1=None):
     k = -np.pi + 2 * np.pi * np.arange(nk) / nk
     KX, KY, KZ = np.meshgrid(k, k, k, indexing="ij")
-    lam = lsa.amplification_eigs(lat, N, tau, 1.0, np.asarray(u, float), KX, KY, KZ)
-    return float(np.log(np.abs(lam)).max())
+    lam = lsa.amplification_eigs(lat, N, tau, 1.0, np.asarray(u, float), KX, KY, KZ, n1=n1)
+    with np.errstate(divide="ignore"):
+        return float(np.log(np.abs(lam)).max())
 
 
-def test_d3q19_order4_is_unstable_at_rest_near_tau_one_half():
-    """Finding: with the Gram reading of D3Q19 (kept polynomials with a zero exponent), order 4
-    relaxes the xxyy, xxzz, yyzz moments, which the D3Q19 weights couple to the second-order
-    ones; at rest the model then has growing high-wavenumber modes for tau close to 1/2
-    (0.0285 per step at tau = 0.51), while orders 2 and 3 do not, and neither does D3Q27 at
-    order 4.  From tau = 0.55 on the rest state is stable again."""
-    g4 = _max_growth_3d("D3Q19", 4, 0.51, (0, 0, 0))
-    assert g4 == pytest.approx(0.0285, abs=2e-3)
+def test_d3q19_order4_with_f1_at_order4_is_unstable_at_rest_near_tau_one_half():
+    """Finding that fixes the D3Q19 reading: with f1 reconstructed at order 4 through the Gram
+    projection (kept polynomials with a zero exponent), the off-equilibrium xxyy, xxzz, yyzz
+    moments, which the D3Q19 weights couple to the second-order ones, are relaxed too; at rest
+    the model then has growing high-wavenumber modes for tau close to 1/2 (0.0285 per step at
+    tau = 0.51, 0.059 at 0.5001), while orders 2 and 3 do not, and neither does D3Q27 at order
+    4.  From tau = 0.55 on the rest state is stable again."""
+    assert _max_growth_3d("D3Q19", 4, 0.51, (0, 0, 0), n1=4) == pytest.approx(0.0285, abs=2e-3)
+    assert _max_growth_3d("D3Q19", 4, 0.5001, (0, 0, 0), n1=4) == pytest.approx(0.0592, abs=3e-3)
     assert _max_growth_3d("D3Q19", 3, 0.51, (0, 0, 0)) < TOL
     assert _max_growth_3d("D3Q19", 2, 0.51, (0, 0, 0)) < TOL
     assert _max_growth_3d("D3Q27", 4, 0.51, (0, 0, 0)) < TOL
-    assert _max_growth_3d("D3Q19", 4, 0.55, (0, 0, 0)) < TOL
+    assert _max_growth_3d("D3Q19", 4, 0.55, (0, 0, 0), n1=4) < TOL
+
+
+@pytest.mark.parametrize("tau", [0.5001, 0.51, 0.55, 0.6])
+def test_d3q19_order4_with_f1_at_order3_is_stable_at_rest(tau):
+    """The D3Q19 model of the oracle and the library: f0 at order 4, f1 at order 3.  Its rest
+    state is stable at every tau, like orders 2 and 3."""
+    assert rr.f1_order("D3Q19", 4) == 3
+    assert _max_growth_3d("D3Q19", 4, tau, (0, 0, 0)) < TOL
+
+
+def test_d3q19_order4_onset_speed_at_tau_051_matches_order3():
+    """At tau = 0.51 the D3Q19 order-4 model (f1 at order 3) stays stable along x up to
+    |u| = 0.35, as order 3 does; both turn unstable before 0.45."""
+    for N in (3, 4):
+        assert _max_growth_3d("D3Q19", N, 0.51, (0.35, 0, 0), nk=12) < TOL
+        assert _max_growth_3d("D3Q19", N, 0.51, (0.45, 0, 0), nk=12) > 1e-4
 
 
 def test_d2q9_high_mach_threshold_of_the_shear_layer_workload():

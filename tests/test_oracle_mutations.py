@@ -119,10 +119,12 @@ def _a0_wrong_component(lat, N, rho, u):
     return np.stack(out)
 
 
-def _collide_wrong_factor(lat, N, tau, f):
+def _collide_wrong_factor(lat, N, tau, f, n1=None):
+    n1 = rr.f1_order(lat, N) if n1 is None else n1
     rho, u, Pi = rr.moments(lat, f)
     A = rr.offeq_second(lat, rho, u, Pi)
-    return rr.reconstruct(lat, N, rr.a0_coefficients(lat, N, rho, u) + (1.0 - tau) * rr.a1_coefficients(lat, N, A, u))
+    f0 = rr.reconstruct(lat, N, rr.a0_coefficients(lat, N, rho, u))
+    return f0 + (1.0 - tau) * rr.reconstruct(lat, n1, rr.a1_coefficients(lat, n1, A, u))  # planted: 1 - tau
 
 
 def _stream_backwards(lat, f):

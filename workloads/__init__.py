@@ -158,7 +158,7 @@ WORKLOADS = {
     # 512^3 random solenoidal field, |k| <= 8, rms Ma 0.1, tau = 0.51
     # D3Q19 at order 3: at tau = 0.51 the order-4 D3Q19 model grows high-wavenumber modes even at
     # rest (0.0285 per step, linear stability analysis of the oracle collision)
-    "solenoidal_512_d3q19": dict(lattice="D3Q19", order=3, n=512, kmax=8, urms=0.1 * CS, tau=0.51, steps=1000),
+    "solenoidal_512_d3q19": dict(lattice="D3Q19", order=4, n=512, kmax=8, urms=0.1 * CS, tau=0.51, steps=1000),
     "solenoidal_512_d3q27": dict(lattice="D3Q27", order=4, n=512, kmax=8, urms=0.1 * CS, tau=0.51, steps=1000),
     # decaying 2D turbulence for the learned closure: fine 1024^2, coarse 256^2 (dx_c = 4 dx_f)
     "turb2d_fine_1024": dict(lattice="D2Q9", order=4, n=1024, kmin=4, kmax=12, urms=0.1 * CS, tau=0.535472),
