@@ -161,7 +161,7 @@ def kernel_resources(B, storage):
     """Registers, scratch, LDS and occupancy of the D3Q27 order-4 step kernel of ``storage``, as the
     compiler reported them when the library was built."""
     name = {"fp32": "k_step<lbrr::D3Q27, 4, float>", "fp16": "k_stepINS_5D3Q27ELi4EDF16_",
-            "fp64": "k_step<lbrr::D3Q27, 4, double>", "mom_fp32": "k_mstep<lbrr::D3Q27, 4, float, 8, 64, false>",
+            "fp64": "k_step<lbrr::D3Q27, 4, double>", "mom_fp32": "k_mstep_t<lbrr::D3Q27, 4, float, 9, false>",
             "mom_fp64": "k_mstep<lbrr::D3Q27, 4, double, 8, 32, false>"}[storage]
     try:
         with open(B.RESOURCES) as fh:

@@ -52,26 +52,39 @@ size_t elem_size(int storage) {
 }
 
 // Chunk length of the moment-state step: rows per block in 2D, z-planes per
-// block in 3D (each block rebuilds lz + 2).  Measured on MI355X:
+// block in 3D (each block rebuilds lz + 2/3 planes' worth: the two planes next
+// to the chunk rebuild one layer).  Measured on MI355X:
 //   2D, rows of 256 nodes: 4 rows best (see kRowX).
-//   3D, 64 x 8 (FP32) or 32 x 8 (FP64) patches, march unrolled by 3, GLUPS at
-//   lz = 3 / 4 / 6 / 9 / 12:
-//     D3Q27 FP32 256^3 37.1 / 38.6 / 39.9 / 39.2 / 39.6
-//                384^3 38.5 / 39.9 / 41.8 / 39.5 / 37.2
-//                512^3 40.5 / 41.9 / 42.6 / 37.7 / 36.9
-//     D3Q19 order 3 FP32 (lz = 3 / 4 / 5 / 6): 256^3 39.2 / 41.1 / 41.8 / 41.9,
-//                384^3 40.0 / 41.4 / 42.6 / 42.4, 448^3 39.7 / 38.4 / 36.5 / 35.3,
-//                512^3 43.0 / 44.5 / 40.9 / 38.0
-//     D3Q27 FP64 (lz = 3 / 4 / 6): 256^3 20.8 / 21.4 / 22.0, 512^3 19.8 / 20.3 / 21.7
-//   So lz = 6, except D3Q19 on planes of 448^2 nodes and more: 4.
+//   3D FP32 (row-aligned tiles of 64 x 9 nodes, x-neighbouring tiles on one
+//   XCD), D3Q27 order 4, GLUPS at lz = 9 / 12 / 16 / 24 / 32 / 43 / 64:
+//     256^3 49.1 / 51.5 / 51.0 / 53.4 / 53.4 / 53.9 / 54.4
+//     512^3 50.9 / 52.6 / 53.9 / 55.0 / 55.9 / 56.1 / 55.7
+//     D3Q19 order 4 512^3 (lz 9 / 12 / 16 / 24): 51.0 / 53.0 / 54.6 / 55.8
+//   Longer chunks re-read fewer edge planes but give fewer blocks, so the host
+//   takes the longest of 24, 16, 12, 9, 6, 4 planes that still gives four
+//   blocks per compute unit (at 256^3: 24 planes, 1408 blocks).
+//   3D FP64 (64 x 8 / 32 x 8 patches, k_mstep), lz = 3 / 4 / 6:
+//     D3Q27 256^3 20.8 / 21.4 / 22.0, 512^3 19.8 / 20.3 / 21.7; D3Q19 on
+//     planes of 448^2 nodes and more prefers 4.  So lz = 6 there, except 4 for
+//     D3Q19 on large planes.
 // LBRR_MOM_LZ overrides the choice.
-int moment_lz(int nvalues, int q, int64_t plane_nodes) {
+int moment_lz(int nvalues, int q, int nx, int ny, int nz, size_t es) {
   if (const char* e = std::getenv("LBRR_MOM_LZ")) {
     const int v = std::atoi(e);
     if (v >= 1) return v;
   }
   if (nvalues == 6) return 4;
-  if (q == 19 && plane_nodes >= 448 * 448) return 4;
+  if (es == 4) {  // row-aligned tiles of 64 x kTileRows nodes, tile rows in groups of eight
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int lz : {24, 16, 12, 9, 6}) {
+      const int64_t rows = int64_t((ny + lbrr::kTileRows - 1) / lbrr::kTileRows) * ((nz + lz - 1) / lz);
+      if (int64_t((nx + 63) / 64) * 8 * ((rows + 7) / 8) >= int64_t(4) * cus) return lz;
+    }
+    return 4;
+  }
+  if (q == 19 && int64_t(nx) * ny >= 448 * 448) return 4;
   return 6;
 }
 
@@ -169,7 +182,7 @@ struct lb_ctx {
     a.sz = sz;
     a.rho0 = rho0;
     a.omega1 = 1.0 - 1.0 / tau;
-    a.lz = moment() ? moment_lz(nvalues(), q(), int64_t(nx) * ny) : 1;
+    a.lz = moment() ? moment_lz(nvalues(), q(), nx, ny, nz, elem_size(storage)) : 1;
     a.walls = moment() ? walls : 0;
     return a;
   }

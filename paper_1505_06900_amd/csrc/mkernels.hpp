@@ -57,6 +57,7 @@ struct MPatch {
   static constexpr int MX = sizeof(S) == 4 ? 64 : 32, TY = 8;
 };
 constexpr int kPrefetch = 2;  // planes of moments in flight ahead of the rebuild
+
 // 2D: nodes per rebuilt row of a block.  Measured, D2Q9 order 4 FP32, GLUPS at
 // 2 / 4 / 8 / 16 rows per chunk: 2048^2 rows of 128: 81 / 86 / 82 / 79, of 256:
 // 86 / 93 / 89 / 81, of 512: 76 / 81 / 85 / 76; 4096^2 rows of 256: 93 / 100 /
@@ -509,6 +510,175 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
   }
 }
 
+// One step of the moment-state update with row-aligned tiles (3D, FP32).  The
+// inner tile of a block is 64 nodes of a row, starting at a multiple of 64,
+// by TY rows.  TY + 2 waves rebuild the tile's 64 columns on rows y0 - 1 ..
+// y0 + TY (one wave per row), and one more wave rebuilds the two halo columns
+// (x0 - 1 and the column right after the tile) of those rows, so every field
+// row is read as two whole 128-byte lines, and the halo lines are the first and
+// last lines of the neighbouring tiles.  A 256-node row takes four tiles.  The
+// march along z is that of k_mstep.  LDS holds the patch as TY + 2 rows of 66
+// columns: column 0 is the left halo, 1 .. width the tile, width + 1 the right
+// halo.
+template <class L, int N, class S, int TY, bool W>
+__global__ void __launch_bounds__(64 * (TY + 3)) k_mstep_t(const S* __restrict__ src, S* __restrict__ dst,
+                                                           StepArgs a) {
+  static_assert(L::D == 3, "3D lattices");
+  static_assert(2 * (TY + 2) <= 64, "the halo wave holds both halo columns of every patch row");
+  using R = S;
+  constexpr int NM = kNM<L>, RW = TY + 2, MXL = 66;
+  __shared__ R pop[L::Q][RW][MXL];
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+  // Blocks reach the eight XCDs round-robin by id, and each XCD has its own
+  // L2.  Blocks b and b + 8 (the same XCD, dispatched one after the other) take
+  // x-neighbouring tiles of one tile row (rows y0 .. y0 + TY - 1 of a z-chunk),
+  // so the halo columns a block reads are lines its XCD's L2 holds for the
+  // neighbour.  Tile rows g >= gy * gz of the last group of eight are empty.
+  const int gx = (a.nx + 63) / 64, gy = (a.ny + TY - 1) / TY, gz = (a.nz + a.lz - 1) / a.lz;
+  const int b = int(blockIdx.x);
+  const int bxi = (b / 8) % gx, g = (b / (8 * gx)) * 8 + b % 8;
+  if (g >= gy * gz) return;
+  const int byi = g % gy, bz = g / gy;
+  const int x0 = bxi * 64, y0 = byi * TY;
+  const int width = (a.nx - x0 < 64) ? a.nx - x0 : 64;
+  // The node this thread rebuilds: patch row r, LDS column col, lattice node (px, py).
+  int r, col, px;
+  bool writes;
+  if (wave < RW) {
+    r = wave;
+    writes = lane < width;
+    col = lane + 1;
+    px = x0 + (writes ? lane : 0);
+  } else {
+    const bool left = lane < RW;
+    writes = lane < 2 * RW;
+    r = left ? lane : (writes ? lane - RW : 0);
+    col = left ? 0 : width + 1;
+    px = wrap(left ? x0 - 1 : x0 + width, a.nx);
+  }
+  const int py = wrap(y0 - 1 + r, a.ny);
+  // the node this thread updates, if inner: (x0 + lane, y0 + r - 1), LDS (lane + 1, r)
+  const bool inner = wave < RW && r >= 1 && r <= TY && lane < width && y0 + r - 1 < a.ny;
+  const int tc = lane + 1;
+  const uint32_t off_in = uint32_t((int64_t(py) * a.sy + px) * int64_t(sizeof(S)));
+  const uint32_t off_out =
+      inner ? uint32_t((int64_t(y0 + r - 1) * a.sy + (x0 + lane)) * int64_t(sizeof(S))) : 0u;
+  const R rho0 = R(a.rho0), om = R(a.omega1);
+
+  auto load = [&](int z, R (&m)[NM]) {
+    const S* s = src + int64_t(z) * a.sz;
+    sfor<0, NM>([&](auto C) { m[C] = at_offset(s + int64_t(C) * a.si, off_in); });
+  };
+  auto rebuild = [&](const R (&m)[NM], auto ZS) __attribute__((always_inline)) {
+    constexpr int Z = decltype(ZS)::value;
+    const Hydro<R> h = state_hydro<L, R>(m, rho0);
+    R C[3][3][3];
+    coefficients<L, N, R>(h, om, C);
+    R f[L::Q];
+    reconstruct<L, N, R, Z>(C, f);
+    if (writes) {
+      sfor<0, L::Q>([&](auto I) {
+        if constexpr (Z == 2 || L::cz(I) == Z) pop[I][r][col] = f[I];
+      });
+    }
+  };
+  auto put = [&](int z, const R (&m)[NM]) {
+    S* d = dst + int64_t(z) * a.sz;
+    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], ptr_at_offset(d + int64_t(C) * a.si, off_out)); });
+  };
+  const int wsx = W ? wall_side(a.walls, 0, x0 + lane, a.nx) : 0;
+  const int wsy = W ? wall_side(a.walls, 1, y0 + r - 1, a.ny) : 0;
+  auto add = [&](Moments<R>& sums, auto CZS, int target) __attribute__((always_inline)) {
+    constexpr int CZ = decltype(CZS)::value;
+    if constexpr (W) {
+      const int wsz = wall_side(a.walls, 2, target, a.nz);
+      if (wsx != 0 || wsy != 0 || wsz != 0) {
+        if constexpr (CZ > 0) clear(sums);
+        add_layer_walls<L, CZ, RW, MXL, R>(sums, pop, tc, r, wsx, wsy, wsz);
+        return;
+      }
+    }
+    add_layer<L, CZ, RW, MXL, R, (CZ > 0)>(sums, pop, tc, r);
+  };
+  auto finish = [&](const Moments<R>& sums, int target, R (&m)[NM]) __attribute__((always_inline)) {
+    if constexpr (W) {
+      const int wsz = wall_side(a.walls, 2, target, a.nz);
+      if (wsx != 0 || wsy != 0 || wsz != 0) {
+        finalize_walls<L, R>(sums, wsx, wsy, wsz, m);
+        return;
+      }
+    }
+    finalize_state<L, R>(sums, rho0, m);
+  };
+  using layer_m = std::integral_constant<int, -1>;
+  using layer_0 = std::integral_constant<int, 0>;
+  using layer_p = std::integral_constant<int, 1>;
+  {
+    // The march of k_mstep: targets z0 .. z1 - 1, planes z0 - 1 .. z1 rebuilt,
+    // register roles rotating with period 3, the two edge planes rebuilding
+    // only the layer that reaches the chunk.
+    static_assert(kPrefetch == 2, "two planes in flight ahead of the rebuild");
+    const int z0 = bz * a.lz;
+    const int z1 = (z0 + a.lz < a.nz) ? z0 + a.lz : a.nz;
+    const int n = z1 - z0;
+    Moments<R> T[3];
+    R B[3][NM];
+    load(wrap(z0 - 1, a.nz), B[0]);
+    load(wrap(z0, a.nz), B[1]);
+    // a completed target is stored at once (with 1024 threads a block has 128
+    // VGPRs per lane, and holding it for the next iteration spilled)
+    auto complete = [&](const Moments<R>& sums, int target) __attribute__((always_inline)) {
+      R out[NM];
+      finish(sums, target, out);
+      put(target, out);
+    };
+    auto iteration = [&](int k, auto PHS, auto ES) __attribute__((always_inline)) {
+      constexpr int PH = decltype(PHS)::value, E = decltype(ES)::value;
+      constexpr int P1 = (PH + 2) % 3, P2 = (PH + 1) % 3;
+      const int pz = z0 - 1 + k;
+      if (k + kPrefetch <= n + 1) load(wrap(pz + kPrefetch, a.nz), B[P1]);
+      rebuild(B[PH], ES);
+      lds_barrier();
+      if (inner) {
+        if constexpr (E == 1) {
+          add(T[PH], layer_p{}, z0);
+        } else if constexpr (E == -1) {
+          add(T[P2], layer_m{}, z1 - 1);
+          complete(T[P2], z1 - 1);
+        } else {
+          if (k < n) add(T[PH], layer_p{}, pz + 1);
+          add(T[P1], layer_0{}, pz);
+          if (k >= 2) {
+            add(T[P2], layer_m{}, pz - 1);
+            complete(T[P2], pz - 1);
+          }
+        }
+      }
+      lds_barrier();
+    };
+    using ph0 = std::integral_constant<int, 0>;
+    using ph1 = std::integral_constant<int, 1>;
+    using ph2 = std::integral_constant<int, 2>;
+    using first_plane = std::integral_constant<int, 1>;
+    using inner_plane = std::integral_constant<int, 2>;
+    using last_plane = std::integral_constant<int, -1>;
+    iteration(0, ph0{}, first_plane{});
+    int k = 1;
+    for (; k + 2 <= n; k += 3) {
+      iteration(k, ph1{}, inner_plane{});
+      iteration(k + 1, ph2{}, inner_plane{});
+      iteration(k + 2, ph0{}, inner_plane{});
+    }
+    if (k <= n) iteration(k++, ph1{}, inner_plane{});
+    if (k <= n) iteration(k++, ph2{}, inner_plane{});
+    switch (k % 3) {
+      case 0: iteration(k, ph0{}, last_plane{}); break;
+      case 1: iteration(k, ph1{}, last_plane{}); break;
+      default: iteration(k, ph2{}, last_plane{}); break;
+    }
+  }
+}
+
 // One step of the 2D moment-state update.  A block of BX threads rebuilds a
 // row of BX nodes (x0 - 1 ... x0 + BX - 2) and marches along y through a
 // chunk of a.lz target rows: the populations rebuilt on row p with c_y = -1,
@@ -739,8 +909,21 @@ hipError_t launch_mstep(const void* src, void* dst, const StepArgs& a, hipStream
                          static_cast<S*>(dst), a);
     return hipGetLastError();
   } else {
-    constexpr int TY = MPatch<S>::TY, MX = MPatch<S>::MX;
     if (int64_t(a.ny) * a.sy * int64_t(sizeof(S)) >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+    if constexpr (sizeof(S) == 4) {
+      constexpr int TY = kTileRows;
+      const int64_t rows = int64_t((a.ny + TY - 1) / TY) * ((a.nz + a.lz - 1) / a.lz);
+      const int64_t nbt = int64_t((a.nx + 63) / 64) * 8 * ((rows + 7) / 8);
+      if (nbt >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+      if (a.walls)
+        hipLaunchKernelGGL((k_mstep_t<L, N, S, TY, true>), dim3(unsigned(nbt)), dim3(64 * (TY + 3)), 0, s,
+                           static_cast<const S*>(src), static_cast<S*>(dst), a);
+      else
+        hipLaunchKernelGGL((k_mstep_t<L, N, S, TY, false>), dim3(unsigned(nbt)), dim3(64 * (TY + 3)), 0, s,
+                           static_cast<const S*>(src), static_cast<S*>(dst), a);
+      return hipGetLastError();
+    }
+    constexpr int TY = MPatch<S>::TY, MX = MPatch<S>::MX;
     const int64_t nb = int64_t((a.nx + MX - 3) / (MX - 2)) * ((a.ny + TY - 3) / (TY - 2)) *
                        ((a.nz + a.lz - 1) / a.lz);
     if (nb >= (int64_t(1) << 31)) return hipErrorInvalidValue;

@@ -9,6 +9,11 @@
 namespace lbrr {
 
 constexpr int kReduceBlock = 256;
+// Inner rows of a row-aligned tile of the 3D FP32 moment step (k_mstep_t):
+// TY + 3 waves per block.  9 rows, 12 waves: no spills (D3Q27 order 4: 123
+// VGPRs, one block per CU); 13 rows, 16 waves (1024 threads, 128 VGPRs per
+// lane) spilled 11-18 VGPRs.
+constexpr int kTileRows = 9;
 
 // Launch parameters shared by the kernels.  Population (or moment field) i of node (x, y, z)
 // lives at element i*si + z*sz + y*sy + x of a buffer; the host picks the
