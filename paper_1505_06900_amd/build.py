@@ -36,6 +36,10 @@ FLAGS = [
     "-Rpass-analysis=kernel-resource-usage",
 ]
 
+# per-source additions: the closure kernels take matrix-core results in ordinary
+# VGPRs, so the activations read them without a copy from the accumulation registers
+SOURCE_FLAGS = {"closure.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 
 def parse_resource_remarks(text):
     """{kernel name: {field: value}} from the compiler's kernel-resource-usage remarks."""
@@ -71,7 +75,8 @@ def hipcc():
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *FLAGS, *SOURCE_FLAGS.get(src, []), "-I", os.path.join(ROOT, "include"), "-c",
+           os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -171,6 +171,18 @@ __device__ __forceinline__ void load_constants(const float* __restrict__ params,
   }
 }
 
+// Standardised BF16 features of one sample into its LDS row (kInP values,
+// inputs kIn .. kInP - 1 zero): (x - mean) * (1 / std).
+__device__ __forceinline__ void write_features(const float (&feat)[kIn], const float* mean, const float* inv,
+                                               uint16_t* row) {
+  bf16x4* xr = reinterpret_cast<bf16x4*>(row);
+  float v[kInP];
+#pragma unroll
+  for (int k = 0; k < kInP; ++k) v[k] = k < kIn ? (feat[k] - mean[k]) * inv[k] : 0.0f;
+#pragma unroll
+  for (int k4 = 0; k4 < kInP / 4; ++k4) xr[k4] = pack_bf16(v[4 * k4], v[4 * k4 + 1], v[4 * k4 + 2], v[4 * k4 + 3]);
+}
+
 // Forward pass of a group of 64 samples shared by NW waves; every thread of
 // the block calls it (barriers inside).  Wave `part` (0..NW-1) of the group
 // computes every NW-th output tile of each layer; wave 0 holds the samples
@@ -180,51 +192,36 @@ __device__ __forceinline__ void load_constants(const float* __restrict__ params,
 // one sample, goes to the sample's LDS row with one 8-byte write and is read
 // back as the next layer's operand with one 8-byte read.  feat: the lane's raw
 // features (wave 0); w: packed weights in LDS; r0, r1: the group's two
-// activation regions; c: constants.
+// activation regions; c: constants.  The barriers wait for LDS only, so global
+// loads a caller issued before the call stay in flight through it.
 template <int NW>
 __device__ __forceinline__ void forward_group(const float (&feat)[kIn], int part, const uint16_t* w, uint16_t* r0,
                                               uint16_t* r1, const float* c, float (&out)[kOut]) {
   const int lane = threadIdx.x & 63, q = lane >> 4;
   if (part == 0) {  // standardised BF16 features, row = sample (stride kLd1, inputs 36..47 zero)
-    bf16x4* xr = reinterpret_cast<bf16x4*>(r0 + lane * kLd1);
-#pragma unroll
-    for (int k4 = 0; k4 < kInP / 4; ++k4) {
-      bf16x4 v;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 4 * k4 + r;
-        v[r] = short(k < kIn ? to_bf16((feat[k] - c[kCMean + k]) * c[kCInv + k]) : uint16_t(0));
-      }
-      xr[k4] = v;
-    }
+    write_features(feat, c + kCMean, c + kCInv, r0 + lane * kLd1);
   }
-  __syncthreads();
+  lds_barrier();
   // layer 1: H1 = gelu(W1 X + b1), 4 x 4 tiles (features j0, samples s0) -> r1
 #pragma unroll
   for (int t = part; t < 16; t += NW) {
-    const int j0 = 16 * (t & 3), s0 = 16 * (t >> 2);
-    f32x4 acc = {0, 0, 0, 0};
+    const int j0 = 16 * (t & 3), s0 = 16 * (t >> 2), j = j0 + 4 * q;
+    f32x4 acc = *reinterpret_cast<const f32x4*>(c + kCB1 + j);
     acc = tile_kc<kInP>(w + kPW1, kLd1, r0, kLd1, j0, s0, acc);
-    const int j = j0 + 4 * q;
-    bf16x4 h;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) h[r] = short(to_bf16(gelu(acc[r] + c[kCB1 + j + r])));
-    *reinterpret_cast<bf16x4*>(r1 + (s0 + (lane & 15)) * kLdH + j) = h;
+    *reinterpret_cast<bf16x4*>(r1 + (s0 + (lane & 15)) * kLdH + j) =
+        pack_bf16(gelu(acc[0]), gelu(acc[1]), gelu(acc[2]), gelu(acc[3]));
   }
-  __syncthreads();
+  lds_barrier();
   // layer 2: H2 = gelu(W2 H1 + b2) -> r0
 #pragma unroll
   for (int t = part; t < 16; t += NW) {
-    const int j0 = 16 * (t & 3), s0 = 16 * (t >> 2);
-    f32x4 acc = {0, 0, 0, 0};
+    const int j0 = 16 * (t & 3), s0 = 16 * (t >> 2), j = j0 + 4 * q;
+    f32x4 acc = *reinterpret_cast<const f32x4*>(c + kCB2 + j);
     acc = tile_kc<kH>(w + kPW2, kLdH, r1, kLdH, j0, s0, acc);
-    const int j = j0 + 4 * q;
-    bf16x4 h;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) h[r] = short(to_bf16(gelu(acc[r] + c[kCB2 + j + r])));
-    *reinterpret_cast<bf16x4*>(r0 + (s0 + (lane & 15)) * kLdH + j) = h;
+    *reinterpret_cast<bf16x4*>(r0 + (s0 + (lane & 15)) * kLdH + j) =
+        pack_bf16(gelu(acc[0]), gelu(acc[1]), gelu(acc[2]), gelu(acc[3]));
   }
-  __syncthreads();
+  lds_barrier();
   // layer 3: Y = W3 H2 + b3 (rows 0..2 of one 16-row tile), FP32 -> r1 as [64][4]
   float* ys = reinterpret_cast<float*>(r1);
 #pragma unroll
@@ -237,12 +234,12 @@ __device__ __forceinline__ void forward_group(const float (&feat)[kIn], int part
       for (int o = 0; o < kOut; ++o) ys[(s0 + lane) * 4 + o] = acc[o] + c[kCB3 + o];
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (part == 0) {
 #pragma unroll
     for (int o = 0; o < kOut; ++o) out[o] = ys[lane * 4 + o] * c[kCYStd + o] + c[kCYMean + o];
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 constexpr int kInferWaves = 2;
@@ -518,65 +515,189 @@ __global__ void __launch_bounds__(256) k_pack(const float* __restrict__ params, 
 // ---------------------------------------------------------------------------
 // Fused coarse D2Q9 step with the closure: pull, moments, features, MLP on the
 // matrix cores, a1^(2) += predicted correction, recursion and reconstruction,
-// store.  A block handles 64 nodes of a row: wave 0 pulls and later collides
-// (one node per lane; lanes past the row end use a wrapped node and do not
-// store) while waves 1-3 compute (rho - rho0, u) of the stored state on rows
-// y-1, y, y+1 (64 + 2 nodes each) into LDS for the neighbour features; then
-// all four waves share the MLP tiles, so a 256^2 grid keeps four waves per
-// SIMD busy.
-constexpr int kClosureNW = 4;
+// store.  A block owns 64 columns of kClosureRows consecutive rows.  Wave w
+// pulls, and later collides, the 64 nodes of row y0 + w (one node per lane;
+// lanes past the row end, or on rows past the last, use a wrapped node and do
+// not store).  (rho - rho0, u) of the stored state on those rows and a
+// one-node halo go to LDS for the neighbour features.  The MLP of the block's
+// kClosureSamples samples is shared: wave w computes output features
+// 16 w .. 16 w + 15 of layers 1 and 2 for every sample, so its slabs of W1 and
+// W2 stay in registers (the biases start its accumulators), and the output
+// layer for its own 64 samples.  Every wave carries the same share of the
+// work, and the barriers wait for LDS only: the pulled populations stay in
+// flight until the collision.
+// One hidden layer for 16 output features j0 .. j0 + 15 of NS x 16 samples:
+// out[s][j] = gelu((W x_s)_j + b_j), K = 16 KC.  w: the wave's slab of W in
+// the matrix-core A layout; in, out: BF16 rows of one sample each (row stride
+// ld_in, kLdH).  Software-pipelined for a single wave per SIMD: the operand
+// reads of tile t + 1 are issued first, then pairs of products of tile t
+// alternate with pairs of activations of tile t - 1, whose arithmetic covers
+// the LDS and matrix-core latencies (two independent activations interleave).
+template <int KC, int NS>
+__device__ __forceinline__ void hidden_layer(const bf16x4 (&w)[KC], f32x4 bias, const uint16_t* in, int ld_in,
+                                             uint16_t* out, int j0) {
+  const int l = threadIdx.x & 63, q = l >> 4, l16 = l & 15;
+  bf16x4 x[2][KC];
+  f32x4 acc[2];
+  auto read = [&](int t, bf16x4(&v)[KC]) __attribute__((always_inline)) {
+    const bf16x4* p = reinterpret_cast<const bf16x4*>(in + (16 * t + l16) * ld_in + 4 * q);
+#pragma unroll
+    for (int c = 0; c < KC; ++c) v[c] = p[4 * c];
+  };
+  auto activate = [&](int t, const f32x4& a) __attribute__((always_inline)) {
+    *reinterpret_cast<bf16x4*>(out + (16 * t + l16) * kLdH + j0 + 4 * q) =
+        pack_bf16(gelu(a[0]), gelu(a[1]), gelu(a[2]), gelu(a[3]));
+  };
+  read(0, x[0]);
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    if (t + 1 < NS) read(t + 1, x[(t + 1) & 1]);
+    // product c of tile t, then activation c of tile t - 1: the accumulation
+    // chain of one tile never holds up the wave's activation arithmetic
+    const f32x4& prev = acc[(t + 1) & 1];
+    float g[4];
+    f32x4 a = bias;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {  // two products and two independent activations per scheduling region
+#pragma unroll
+      for (int c = 2 * r; c < 2 * r + 2; ++c)
+        if (c < KC) a = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[c], x[t & 1][c], a, 0, 0, 0);
+      if (t > 0) {
+        g[2 * r] = gelu(prev[2 * r]);
+        g[2 * r + 1] = gelu(prev[2 * r + 1]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (t > 0)
+      *reinterpret_cast<bf16x4*>(out + (16 * (t - 1) + l16) * kLdH + j0 + 4 * q) = pack_bf16(g[0], g[1], g[2], g[3]);
+    acc[t & 1] = a;
+  }
+  activate(NS - 1, acc[(NS - 1) & 1]);
+}
+
+// v mod n for v >= -1 (periodic index of a halo node): one compare and add
+// or subtract in the usual case, the division only for axes shorter than the
+// tile and its halo.
+__device__ __forceinline__ int wrap(int v, int n) {
+  if (v < 0) v += n;
+  if (v >= n) v -= n;
+  return v < n ? v : v % n;
+}
+
+constexpr int kClosureRows = 4;
+constexpr int kClosureSamples = 64 * kClosureRows;
+constexpr int kClosureHalo = (kClosureRows + 2) * 66;  // nodes whose moments the features read
 
 template <int N, class S>
-__global__ void __launch_bounds__(64 * kClosureNW) k_step_closure(const S* __restrict__ src, S* __restrict__ dst, StepArgs a,
-                                                                  const uint16_t* __restrict__ packed,
-                                                                  const float* __restrict__ params,
-                                                                  const float* __restrict__ norm) {
+__global__ void __launch_bounds__(kClosureSamples)
+    k_step_closure(const S* __restrict__ src, S* __restrict__ dst, StepArgs a, const uint16_t* __restrict__ packed,
+                   const float* __restrict__ params, const float* __restrict__ norm) {
   using R = typename Prec<S>::R;
-  __shared__ __attribute__((aligned(16))) uint16_t w[kNPacked];
-  __shared__ __attribute__((aligned(16))) uint16_t reg[2][kRegion];
-  __shared__ __attribute__((aligned(16))) float cst[kNConst];
-  __shared__ float nb[3][66][3];  // (rho - rho0, u) of rows y-1, y, y+1 at x0-1 .. x0+64
-  load_weights<64 * kClosureNW>(packed, w);
-  load_constants(params, norm, cst);
-  const int part = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int x0 = blockIdx.x * 64, xr = x0 + lane;
-  const bool active = xr < a.nx;
-  const int x = active ? xr : xr % a.nx;
-  const int y = blockIdx.y;
+  __shared__ __attribute__((aligned(16))) uint16_t r0[kClosureSamples * kLdH];
+  __shared__ __attribute__((aligned(16))) uint16_t r1[kClosureSamples * kLdH];
+  __shared__ __attribute__((aligned(16))) float cst[kNNorm];  // x_mean, 1 / x_std, y_mean, y_std
+  __shared__ __attribute__((aligned(16))) float nb[kClosureRows + 2][66][4];  // (rho - rho0, u_x, u_y, -)
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, l16 = lane & 15;
+  const int gx = (a.nx + 63) / 64;
+  const int x0 = int(blockIdx.x % unsigned(gx)) * 64, y0 = int(blockIdx.x / unsigned(gx)) * kClosureRows;
+  const int xr = x0 + lane, yr = y0 + wave;
+  const bool active = xr < a.nx && yr < a.ny;
+  const int x = xr < a.nx ? xr : xr % a.nx, y = yr < a.ny ? yr : yr % a.ny;
+  // global loads first: one normalisation constant per thread, the lane's
+  // pulled populations, the stored populations of the halo nodes, the wave's
+  // weight slabs and its bias values (consumed in this order, so that no wait
+  // for one load waits for a later one)
+  const float nv = threadIdx.x < kNNorm ? norm[threadIdx.x] : 0.0f;
   R f[9];
-  if (part == 0) {
-    pull9<S, R>(src, a, x, y, f);
-  } else if (part <= 3) {
-    const int yy = (y + part - 2 + a.ny) % a.ny;
-    for (int k = lane; k < 66; k += 64) {
-      const int xx = ((x0 - 1 + k) % a.nx + a.nx) % a.nx;
-      float v[3];
-      node_moments3<S>(src, a, int64_t(yy) * a.sy + xx, v);
-      nb[part - 1][k][0] = v[0];
-      nb[part - 1][k][1] = v[1];
-      nb[part - 1][k][2] = v[2];
+  pull9<S, R>(src, a, x, y, f);
+  constexpr int kPer = (kClosureHalo + kClosureSamples - 1) / kClosureSamples;
+  R p[kPer][9];
+#pragma unroll
+  for (int h = 0; h < kPer; ++h) {
+    const int k = int(threadIdx.x) + h * kClosureSamples;
+    if (k < kClosureHalo) {
+      const int64_t off = int64_t(wrap(y0 - 1 + k / 66, a.ny)) * a.sy + wrap(x0 - 1 + k % 66, a.nx);
+      sfor<0, 9>([&](auto I) { p[h][I] = R(src[int64_t(I) * a.si + off]); });
     }
   }
-  __syncthreads();
-  float feat[kIn];
-  if (part == 0) {
+  const int j0 = 16 * wave;
+  const bf16x4* pw = reinterpret_cast<const bf16x4*>(packed);
+  bf16x4 w1[kInP / 16], w2[kH / 16], w3[kH / 16];
+#pragma unroll
+  for (int c = 0; c < kInP / 16; ++c) w1[c] = pw[(kPW1 + (j0 + l16) * kLd1 + 4 * q + 16 * c) / 4];
+#pragma unroll
+  for (int c = 0; c < kH / 16; ++c) {
+    w2[c] = pw[(kPW2 + (j0 + l16) * kLdH + 4 * q + 16 * c) / 4];
+    w3[c] = pw[(kPW3 + l16 * kLdH + 4 * q + 16 * c) / 4];
+  }
+  const f32x4 b1 = *reinterpret_cast<const f32x4*>(params + kOffB1 + j0 + 4 * q);
+  const f32x4 b2 = *reinterpret_cast<const f32x4*>(params + kOffB2 + j0 + 4 * q);
+  const f32x4 b3 = q == 0 ? f32x4{params[kOffB3], params[kOffB3 + 1], params[kOffB3 + 2], 0.0f} : f32x4{0, 0, 0, 0};
+  if (threadIdx.x < kNNorm) cst[threadIdx.x] = (threadIdx.x >= kIn && threadIdx.x < 2 * kIn) ? 1.0f / nv : nv;
+  // halo moments -> LDS
+#pragma unroll
+  for (int h = 0; h < kPer; ++h) {
+    const int k = int(threadIdx.x) + h * kClosureSamples;
+    if (k < kClosureHalo) {
+      const Moments<R> mo = raw_moments<D2Q9, R>(p[h]);
+      const Hydro<R> hh = hydro<D2Q9, R>(mo, R(a.rho0));
+      *reinterpret_cast<f32x4*>(&nb[k / 66][k % 66][0]) = f32x4{float(hh.drho), float(hh.ux), float(hh.uy), 0.0f};
+    }
+  }
+  lds_barrier();
+  // features of the lane's node -> its row of r0
+  {
+    float feat[kIn];
 #pragma unroll
     for (int i = 0; i < 9; ++i) feat[i] = float(f[i]);
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx)
+      for (int dx = 0; dx < 3; ++dx) {
+        const f32x4 v = *reinterpret_cast<const f32x4*>(&nb[wave + dy][lane + dx][0]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) feat[9 + 3 * (3 * dy + dx) + c] = nb[dy][lane + dx][c];
+        for (int c = 0; c < 3; ++c) feat[9 + 3 * (3 * dy + dx) + c] = v[c];
+      }
+    write_features(feat, cst, cst + kIn, r0 + threadIdx.x * kLd1);
   }
-  float d[kOut];
-  forward_group<kClosureNW>(feat, part, w, reg[0], reg[1], cst, d);
-  if (part != 0) return;
+  lds_barrier();
+  // layer 1: H1 = gelu(W1 X + b1), features j0 .. j0 + 15 of every sample -> r1
+  hidden_layer<kInP / 16, kClosureSamples / 16>(w1, b1, r0, kLd1, r1, j0);
+  lds_barrier();
+  // layer 2: H2 = gelu(W2 H1 + b2) -> r0
+  hidden_layer<kH / 16, kClosureSamples / 16>(w2, b2, r1, kLdH, r0, j0);
+  lds_barrier();
+  // layer 3: Y = W3 H2 + b3 for the wave's own samples, FP32 -> r1 as [sample][4]
+  float* ys = reinterpret_cast<float*>(r1);
+  {
+    // four independent tiles, their products interleaved so that no product waits for the previous one
+    bf16x4 hv[4][kH / 16];
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bf16x4* hb = reinterpret_cast<const bf16x4*>(r0 + (64 * wave + 16 * t + l16) * kLdH + 4 * q);
+#pragma unroll
+      for (int c = 0; c < kH / 16; ++c) hv[t][c] = hb[4 * c];
+      acc[t] = b3;
+    }
+#pragma unroll
+    for (int c = 0; c < kH / 16; ++c)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3[c], hv[t][c], acc[t], 0, 0, 0);
+    if (q == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) *reinterpret_cast<f32x4*>(ys + (64 * wave + 16 * t + l16) * 4) = acc[t];
+    }
+  }
+  lds_barrier();
+  const f32x4 yv = *reinterpret_cast<const f32x4*>(ys + threadIdx.x * 4);
   const Moments<R> mo = raw_moments<D2Q9, R>(f);
   Hydro<R> h = hydro<D2Q9, R>(mo, R(a.rho0));
-  h.axx += R(d[0]);
-  h.axy += R(d[1]);
-  h.ayy += R(d[2]);
+  const float* ym = cst + 2 * kIn;
+  const float* ysd = ym + kOut;
+  h.axx += R(yv[0] * ysd[0] + ym[0]);
+  h.axy += R(yv[1] * ysd[1] + ym[1]);
+  h.ayy += R(yv[2] * ysd[2] + ym[2]);
   R C[3][3][3];
   coefficients<D2Q9, N, R>(h, R(a.omega1), C);
   reconstruct<D2Q9, N, R>(C, f);
@@ -589,8 +710,10 @@ __global__ void __launch_bounds__(64 * kClosureNW) k_step_closure(const S* __res
 template <class S>
 hipError_t step_closure_s(int order, const void* src, void* dst, const StepArgs& a, const uint16_t* packed,
                           const float* params, const float* norm, hipStream_t s) {
-  dim3 grid((a.nx + 63) / 64, a.ny, 1);
-  const int bx = 64 * kClosureNW;
+  const int64_t blocks = int64_t((a.nx + 63) / 64) * ((a.ny + kClosureRows - 1) / kClosureRows);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  dim3 grid(unsigned(blocks), 1, 1);
+  const int bx = kClosureSamples;
   switch (order) {
     case 2:
       hipLaunchKernelGGL((k_step_closure<2, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),

@@ -41,6 +41,16 @@ __device__ __forceinline__ int64_t node_offset(const StepArgs& a, uint32_t n) {
   return int64_t(z) * a.sz + int64_t(y) * a.sy + x;
 }
 
+// Block barrier for an LDS exchange: waits for the LDS accesses of every wave
+// but leaves global loads and stores in flight (for kernels whose threads
+// share nothing through global memory within a launch), so a prefetch
+// survives the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // Fused pull-streaming + regularised collision, one thread per node.
 //

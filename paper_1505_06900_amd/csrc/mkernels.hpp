@@ -336,15 +336,6 @@ __device__ __forceinline__ void finalize_walls(const Moments<R>& s, int sx, int 
   }
 }
 
-// Block barrier for the LDS exchange: waits for the LDS accesses of every
-// wave but leaves global loads and stores in flight (threads of a block share
-// nothing through global memory here), so a prefetch survives the barrier.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // Element at a byte offset from a base pointer.
 template <class S>
 __device__ __forceinline__ S at_offset(const S* base, uint32_t off) {

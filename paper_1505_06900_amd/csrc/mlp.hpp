@@ -52,15 +52,41 @@ __device__ __forceinline__ float erf_as(float x, float& g) {
   return x < 0.0f ? -e : e;
 }
 
-// GELU with the error function (exact form 0.5 z (1 + erf(z / sqrt 2))) and its derivative.
+// GELU in the exact erf form, gelu(z) = z Phi(z) (Phi: standard normal
+// distribution function), evaluated as max(z, 0) - |z| Phi(-|z|), an identity
+// for every z.  Phi(-x) = 2^H(x) with x = min(|z|, 6) and H the degree-6
+// polynomial below, fitted to log2 Phi(-x) on [0, 6] for the smallest largest
+// error of x Phi(-x) (Lawson's iteratively reweighted least squares; the fit is
+// gelu_fit.py beside this package).  FP32 error on [-12, 12]: at most 2.8e-7,
+// 8.1e-8 beyond half an ulp of the result (erf by A&S 7.1.26 above: 3.8e-7);
+// beyond |z| = 6 the term dropped is below 6e-9 |z|.  One exponential and
+// nine other operations, against two transcendentals and about seventeen.
+constexpr float kGeluH[7] = {-9.999930859e-01f, -1.151201725e+00f, -4.587709904e-01f, -5.341210216e-02f,
+                             8.080714382e-03f,  -7.692191284e-04f, 3.309273961e-05f};
 __device__ __forceinline__ float gelu(float z) {
-  float g;
-  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f, g));
+  // the clamps as medians of three: min(|z|, 6) and max(z, 0) in one operation each
+  const float x = __builtin_amdgcn_fmed3f(fabsf(z), 0.0f, 6.0f);
+  float h = kGeluH[6];
+#pragma unroll
+  for (int k = 5; k >= 0; --k) h = fmaf(h, x, kGeluH[k]);
+  return fmaf(-fabsf(z), __builtin_amdgcn_exp2f(h), __builtin_amdgcn_fmed3f(z, 0.0f, 3.40282347e38f));
 }
+// Derivative of the erf form, Phi(z) + z phi(z), with erf by A&S 7.1.26.
 __device__ __forceinline__ float gelu_grad(float z) {
   float g;  // exp(-z^2 / 2)
   const float e = erf_as(z * 0.70710678118654752f, g);
   return 0.5f * (1.0f + e) + z * g * 0.39894228040143268f;
+}
+
+// Four FP32 values -> four BF16 values, round to nearest even (the matrix
+// cores' operand layout: element r in bits 16 r .. 16 r + 15 of the pair).
+__device__ __forceinline__ bf16x4 pack_bf16(float a, float b, float c, float d) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 lo = __builtin_convertvector((f32x2){a, b}, bf16x2);
+  const bf16x2 hi = __builtin_convertvector((f32x2){c, d}, bf16x2);
+  return __builtin_bit_cast(bf16x4, ((u32x2){__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi)}));
 }
 
 // One 16 x 16 output tile of A (M x K) * B (K x N) from BF16 values in LDS:

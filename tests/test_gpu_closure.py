@@ -161,10 +161,13 @@ def _oracle_closure_step(g, params, norm, tau):
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
-def test_fused_closure_step(lbrr, gpu, storage):
+@pytest.mark.parametrize("ny,nx", [(24, 200), (25, 130)])
+def test_fused_closure_step(lbrr, gpu, storage, ny, nx):
+    """Rows of 4 and 3 64-node segments with ragged ends; 96 and 75 segments, so the blocks,
+    which take every gridDim.x-th segment, run 4 segments each, and 4 or 3."""
     torch = gpu
     L = OL.lattice("D2Q9")
-    ny, nx, tau = 24, 200, 0.58  # two 128-node blocks per row, ragged
+    tau = 0.58
     rho, u, pi1 = (1.0 + W.smooth_random(1, (1, ny, nx), 0.02, 31)[0], W.smooth_random(2, (1, ny, nx), 0.06, 32),
                    W.smooth_random(3, (1, ny, nx), 1e-3, 33))
     wr = L.w[:, None, None, None]
