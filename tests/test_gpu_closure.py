@@ -1,12 +1,14 @@
 """GPU parity of the learned-closure kernels against the FP64 closure oracle.
 
 Bars: coarse-graining 1e-12 (FP64 in, FP64 out); features 1e-6 relative to
-their scale (FP32 outputs of an FP64 state); MLP outputs and gradients
-within 2e-3 of the oracle (same BF16 rounding points, FP32 vs FP64
-accumulation: a rare one-ulp BF16 flip of an activation moves an output by
-about 2^-8 of its size); Adam 1e-6; the fused closure step with a zero
-network equals the plain step, and with a random network matches the oracle
-collision with the predicted correction added to a1^(2).
+their scale (FP32 outputs of an FP64 state); MLP outputs within 2e-3 of the
+oracle at the worst sample and 1e-5 at the median (same BF16 rounding points,
+FP32 vs FP64 accumulation: a rare one-ulp BF16 flip of an activation moves an
+output by about 2^-8 of its size); the batch gradient within 1e-3 relative
+(measured 1.3e-4) and each layer's block within 2e-3; Adam 1e-6; the fused
+closure step with a zero network equals the plain step, and with a random
+network matches the oracle collision with the predicted correction added to
+a1^(2).
 """
 import ctypes
 
@@ -128,11 +130,12 @@ def test_mlp_gradient_and_adam_match_oracle(lbrr, gpu):
     rel = np.linalg.norm(g1 - g_ref) / np.linalg.norm(g_ref)
     print(f"loss gpu {loss.item():.6f} oracle {l_ref:.6f}; gradient rel err {rel:.2e}")
     assert loss.item() == pytest.approx(l_ref, rel=1e-3)
-    assert rel <= 2e-3
+    assert rel <= 1e-3
     for name, (o, n) in {"W1": (0, 2304), "b1": (2304, 2368), "W2": (2368, 6464), "b2": (6464, 6528),
                          "W3": (6528, 6720), "b3": (6720, 6723)}.items():
         r = np.linalg.norm(g1[o:n] - g_ref[o:n]) / np.linalg.norm(g_ref[o:n])
-        assert r <= 5e-3, (name, r)
+        print(f"  {name} rel err {r:.2e}")
+        assert r <= 2e-3, (name, r)
     # Adam, two steps
     m = torch.zeros_like(pt)
     v = torch.zeros_like(pt)
