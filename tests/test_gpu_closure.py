@@ -164,10 +164,12 @@ def _oracle_closure_step(g, params, norm, tau):
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
-@pytest.mark.parametrize("ny,nx", [(24, 200), (25, 130)])
+@pytest.mark.parametrize("ny,nx", [(24, 200), (25, 130), (3, 10), (1, 70)])
 def test_fused_closure_step(lbrr, gpu, storage, ny, nx):
     """Rows of 4 and 3 tiles of 64 columns with ragged ends; the fused step's blocks cover 4 rows,
-    so at ny = 25 the last block row holds one row of the grid and three past it.
+    so at ny = 25 the last block row holds one row of the grid and three past it.  The tiny
+    periodic boxes (3 x 10, 1 x 70) wrap the neighbour halo several times over.  Three more
+    steps check the state carried from one closure step to the next.
 
     FP16 storage: the oracle starts from the FP16-rounded deviations the library stores, and the
     bar adds one FP16 rounding of the stored outputs (2^-11 of the largest deviation)."""
@@ -210,5 +212,13 @@ def test_fused_closure_step(lbrr, gpu, storage, ny, nx):
     print(f"closure effect {effect:.3e}, gpu-oracle {err:.3e}, storage rounding allowance {store:.1e}")
     assert effect > 1e-6
     assert err <= 2e-3 * effect + store
+    # three more closure steps from the state reached (the oracle from its own state)
+    for _ in range(3):
+        clos.step(1)
+        ref, _ = _oracle_closure_step(ref, params, norm, tau)
+    got = clos.get_populations().cpu().numpy().astype(np.float64)
+    err4 = np.abs(got - (ref - wr)).max()
+    print(f"  after 4 closure steps: gpu-oracle {err4:.3e}")
+    assert err4 <= 4 * (2e-3 * effect + store)
     plain.close()
     clos.close()
