@@ -3,8 +3,10 @@
 Against the FP64 oracle (`oracle/walls.py`) on the same seeded inputs, with the velocity set to 0
 on the wall nodes: rho, u, pi1 after several steps for every lattice and order, walls on one,
 two or three axes (edges and corners included), population and moment storage, FP64 bar
-1e-12 / 1e-10, FP32 1e-5 / 1e-4; enstrophy with one-sided wall differences; the rest state of a
-closed box; the channel shear mode decay rate on the GPU; argument checks.
+1e-12 / 1e-10, FP32 1e-5 / 1e-4; FP16 population storage 2e-3 / 1e-2 (deviations with 11
+significant bits, rounded at every store: measured at most 6.5e-4 on u and 3.9e-3 on pi1 after
+these 16 / 6 steps); enstrophy with one-sided wall differences (FP16: 2e-4, measured 3.4e-5);
+the rest state of a closed box; the channel shear mode decay rate on the GPU; argument checks.
 """
 import numpy as np
 import pytest
@@ -16,7 +18,9 @@ from oracle import walls as OW
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-5, 1e-4), "mom_fp64": (1e-12, 1e-10), "mom_fp32": (1e-5, 1e-4)}
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-5, 1e-4), "mom_fp64": (1e-12, 1e-10), "mom_fp32": (1e-5, 1e-4),
+       "fp16": (2e-3, 1e-2)}
+ENS_TOL = {"fp64": 1e-12, "mom_fp64": 1e-12, "fp32": 1e-4, "mom_fp32": 1e-4, "fp16": 2e-4}
 WALLS = {2: [(True, True, False), (False, True, False), (True, False, False)],
          3: [(True, True, True), (False, True, False), (True, True, False)]}
 SHAPES = {2: (1, 23, 300), 3: (7, 9, 70)}
@@ -60,7 +64,7 @@ def gpu_walls(P, lat, N, tau, shape, walls, steps, seed, storage):
     return r, v, p, ens
 
 
-@pytest.mark.parametrize("storage", ["fp64", "fp32", "mom_fp64", "mom_fp32"])
+@pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16", "mom_fp64", "mom_fp32"])
 @pytest.mark.parametrize("lat,N", TP.CASES)
 def test_walls_parity_with_oracle(lbrr, gpu, lat, N, storage):
     L = OL.lattice(lat)
@@ -74,8 +78,10 @@ def test_walls_parity_with_oracle(lbrr, gpu, lat, N, storage):
         e = [max(TP.rel_l2(g, r), TP.rel_linf(g, r)) for g, r in zip(got[:3], ref[:3])]
         e_ens = abs(got[3] - ref[3]) / ref[3]
         print(f"  err rho {e[0]:.2e} u {e[1]:.2e} pi1 {e[2]:.2e} enstrophy {e_ens:.2e}", flush=True)
-        assert e[0] <= tol_ru and e[1] <= tol_ru and e[2] <= tol_pi
-        assert e_ens <= (1e-12 if storage.endswith("fp64") else 1e-4)
+        assert e[0] <= tol_ru and e[1] <= tol_ru
+        if tol_pi is not None:
+            assert e[2] <= tol_pi
+        assert e_ens <= ENS_TOL[storage]
 
 
 @pytest.mark.parametrize("storage", ["fp64", "mom_fp64"])
