@@ -4,9 +4,10 @@ Bar (relative to the reference field):
   rho, u      L2 and Linf <= 1e-12 with FP64 storage, <= 1e-5 with FP32;
   pi1         <= 1e-10 (FP64) / 1e-4 (FP32): a1^(2) is a small difference of
               O(1) moments, so its relative rounding is larger;
-  FP16        velocity error reported and bounded loosely (5e-3 after the
-              short runs here), since half-precision deviations carry about
-              11 significant bits.
+  FP16        rho, u <= 2e-3 and pi1 <= 2e-2: half-precision deviations carry
+              11 significant bits and are rounded at every store (measured
+              after the 24 / 8 steps here: u at most 8.9e-4, rho 2.8e-5,
+              pi1 6.1e-3).
 Sizes span several x-blocks with a ragged tail (nx = 300 -> blocks of 256)
 and small sub-wave rows (nx = 20), and every lattice / order / storage.
 """
@@ -22,7 +23,7 @@ from oracle import rr
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-5, 1e-4), "fp16": (5e-3, None)}
+TOL = {"fp64": (1e-12, 1e-10), "fp32": (1e-5, 1e-4), "fp16": (2e-3, 2e-2)}
 CASES = [(lat, N) for lat in ("D2Q9", "D3Q19", "D3Q27") for N in range(2, OL.MAX_ORDER[lat] + 1)]
 SHAPES = {2: [(1, 37, 70), (1, 9, 300)], 3: [(6, 10, 300), (12, 14, 20)]}
 
