@@ -258,7 +258,8 @@ def test_full_size_sampled_parity(lbrr, gpu, name, storage):
     g2 = _neighbourhood_step(L, N, tau, pts, g1, shape)
     r_ref, u_ref, _ = rr.moments(L, g2)
     idx = tuple(pts.T)
-    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 5e-3, "mom_fp64": 1e-12, "mom_fp32": 1e-5}[storage]
+    # FP16: one rounding of 11-bit deviations per store (measured at most 4.1e-4 on u, 2.3e-4 on rho)
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16": 2e-3, "mom_fp64": 1e-12, "mom_fp32": 1e-5}[storage]
     e_r = np.abs(r_gpu[idx] - r_ref).max()
     e_u = np.abs(u_gpu[(slice(None),) + idx] - u_ref).max() / np.abs(u_ref).max()
     print(f"  sampled err rho {e_r:.2e} u {e_u:.2e}", flush=True)
