@@ -705,13 +705,14 @@ int lb_set_closure(lb_handle h, const float* params, const float* norm, int enab
   if (!h->cl_params) {
     HIP_TRY(hipMalloc(&h->cl_params, sizeof(float) * lbrr::kMlpNParam), "hipMalloc closure params");
     HIP_TRY(hipMalloc(&h->cl_norm, sizeof(float) * lbrr::kMlpNNorm), "hipMalloc closure norm");
-    HIP_TRY(hipMalloc(&h->cl_packed, sizeof(uint16_t) * lbrr::kMlpNPacked), "hipMalloc closure weights");
+    HIP_TRY(hipMalloc(&h->cl_packed, sizeof(uint16_t) * (lbrr::kMlpNPacked + lbrr::kMlpNRegImage)),
+            "hipMalloc closure weights");
   }
   HIP_TRY(hipMemcpyAsync(h->cl_params, params, sizeof(float) * lbrr::kMlpNParam, hipMemcpyDeviceToDevice, h->stream),
           "copy closure params");
   HIP_TRY(hipMemcpyAsync(h->cl_norm, norm, sizeof(float) * lbrr::kMlpNNorm, hipMemcpyDeviceToDevice, h->stream),
           "copy closure norm");
-  hipError_t e = lbrr::mlp_pack(h->cl_params, h->cl_packed, h->stream);
+  hipError_t e = lbrr::mlp_pack_step(h->cl_params, h->cl_packed, h->stream);
   if (e != hipSuccess) return hip_fail(e, "pack closure weights");
   h->closure_on = true;
   return LB_OK;

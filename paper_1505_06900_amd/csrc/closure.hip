@@ -513,66 +513,22 @@ __global__ void __launch_bounds__(256) k_pack(const float* __restrict__ params, 
 }
 
 // ---------------------------------------------------------------------------
-// Fused coarse D2Q9 step with the closure: pull, moments, features, MLP on the
-// matrix cores, a1^(2) += predicted correction, recursion and reconstruction,
-// store.  A block owns 64 columns of kClosureRows consecutive rows.  Wave w
-// pulls, and later collides, the 64 nodes of row y0 + w (one node per lane;
-// lanes past the row end, or on rows past the last, use a wrapped node and do
-// not store).  (rho - rho0, u) of the stored state on those rows and a
-// one-node halo go to LDS for the neighbour features.  The MLP of the block's
-// kClosureSamples samples is shared: wave w computes output features
-// 16 w .. 16 w + 15 of layers 1 and 2 for every sample, so its slabs of W1 and
-// W2 stay in registers (the biases start its accumulators), and the output
-// layer for its own 64 samples.  Every wave carries the same share of the
-// work, and the barriers wait for LDS only: the pulled populations stay in
-// flight until the collision.
-// One hidden layer for 16 output features j0 .. j0 + 15 of NS x 16 samples:
-// out[s][j] = gelu((W x_s)_j + b_j), K = 16 KC.  w: the wave's slab of W in
-// the matrix-core A layout; in, out: BF16 rows of one sample each (row stride
-// ld_in, kLdH).  Software-pipelined for a single wave per SIMD: the operand
-// reads of tile t + 1 are issued first, then pairs of products of tile t
-// alternate with pairs of activations of tile t - 1, whose arithmetic covers
-// the LDS and matrix-core latencies (two independent activations interleave).
-template <int KC, int NS>
-__device__ __forceinline__ void hidden_layer(const bf16x4 (&w)[KC], f32x4 bias, const uint16_t* in, int ld_in,
-                                             uint16_t* out, int j0) {
-  const int l = threadIdx.x & 63, q = l >> 4, l16 = l & 15;
-  bf16x4 x[2][KC];
-  f32x4 acc[2];
-  auto read = [&](int t, bf16x4(&v)[KC]) __attribute__((always_inline)) {
-    const bf16x4* p = reinterpret_cast<const bf16x4*>(in + (16 * t + l16) * ld_in + 4 * q);
-#pragma unroll
-    for (int c = 0; c < KC; ++c) v[c] = p[4 * c];
-  };
-  auto activate = [&](int t, const f32x4& a) __attribute__((always_inline)) {
-    *reinterpret_cast<bf16x4*>(out + (16 * t + l16) * kLdH + j0 + 4 * q) =
-        pack_bf16(gelu(a[0]), gelu(a[1]), gelu(a[2]), gelu(a[3]));
-  };
-  read(0, x[0]);
-#pragma unroll
-  for (int t = 0; t < NS; ++t) {
-    if (t + 1 < NS) read(t + 1, x[(t + 1) & 1]);
-    // product c of tile t, then activation c of tile t - 1: the accumulation
-    // chain of one tile never holds up the wave's activation arithmetic
-    const f32x4& prev = acc[(t + 1) & 1];
-    float g[4];
-    f32x4 a = bias;
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {  // two products and two independent activations per scheduling region
-#pragma unroll
-      for (int c = 2 * r; c < 2 * r + 2; ++c)
-        if (c < KC) a = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[c], x[t & 1][c], a, 0, 0, 0);
-      if (t > 0) {
-        g[2 * r] = gelu(prev[2 * r]);
-        g[2 * r + 1] = gelu(prev[2 * r + 1]);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    if (t > 0)
-      *reinterpret_cast<bf16x4*>(out + (16 * (t - 1) + l16) * kLdH + j0 + 4 * q) = pack_bf16(g[0], g[1], g[2], g[3]);
-    acc[t & 1] = a;
-  }
-  activate(NS - 1, acc[(NS - 1) & 1]);
+// Matrix-core operands of the fused step: the 16 x 16 x 32 BF16 product, whose
+// lane l supplies eight consecutive k of row (A) or column (B) l % 16 from k
+// offset 8 (l / 16) of a 32-wide chunk.  A and B take the same k assignment,
+// so the product sums matching pairs whatever order the hardware uses.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf16x8 join8(bf16x4 lo, bf16x4 hi) {
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+// Eight BF16 values at k = 32 c + 8 q of a row (p: the row's start, 8-byte
+// aligned), zero where k >= kv (the zero padding of a shorter operand).
+__device__ __forceinline__ bf16x8 operand8(const uint16_t* p, int c, int q, int kv) {
+  const bf16x4* v = reinterpret_cast<const bf16x4*>(p + 32 * c + 8 * q);
+  const bf16x8 x = join8(v[0], v[1]);
+  return 32 * c + 8 * q < kv ? x : bf16x8{};
 }
 
 // v mod n for v >= -1 (periodic index of a halo node): one compare and add
@@ -588,13 +544,57 @@ constexpr int kClosureRows = 4;
 constexpr int kClosureSamples = 64 * kClosureRows;
 constexpr int kClosureHalo = (kClosureRows + 2) * 66;  // nodes whose moments the features read
 
+// A operand of a product whose k runs over the 64 outputs of the previous
+// layer as the matrix cores leave them in registers: lane (q, l16) holds rows
+// 4 q .. 4 q + 3 of each 16-row output tile, so chunk c of the next product
+// takes elements 0..3 from tile 2 c and 4..7 from tile 2 c + 1, i.e.
+// k = 32 c + 16 (i / 4) + 4 q + i % 4.  row: the weight row (output feature).
+__device__ __forceinline__ bf16x8 operand8_tiles(const uint16_t* row, int c, int q) {
+  const bf16x4* v = reinterpret_cast<const bf16x4*>(row + 32 * c + 4 * q);
+  return join8(v[0], v[4]);
+}
+
+// The fused step's weight operands as its lanes hold them: operand o (0-7:
+// W1 tile jt = o / 2, chunk c = o % 2; 8-15: W2 likewise; 16-17: W3 chunk c),
+// lane (q, l16), eight BF16 values: image[(o * 64 + lane) * 8 + e].  A lane
+// then fetches each operand with one 16-byte load, the wave's 64 loads of an
+// operand being one contiguous KiB.  Built from the packed weights.
+constexpr int kNOps = 18;
+static_assert(kMlpNRegImage == kNOps * 64 * 8, "closure.hpp sizes");
+
+__device__ __forceinline__ bf16x8 step_operand(const uint16_t* packed, int o, int lane) {
+  const int q = lane >> 4, l16 = lane & 15;
+  if (o < 8) return operand8(packed + kPW1 + (16 * (o >> 1) + l16) * kLd1, o & 1, q, kInP);
+  if (o < 16) return operand8_tiles(packed + kPW2 + (16 * ((o - 8) >> 1) + l16) * kLdH, o & 1, q);
+  return operand8_tiles(packed + kPW3 + l16 * kLdH, o - 16, q);
+}
+
+__global__ void __launch_bounds__(64) k_pack_image(const uint16_t* __restrict__ packed, bf16x8* __restrict__ image) {
+  const int o = blockIdx.x;  // one operand per block, one lane per thread
+  image[o * 64 + threadIdx.x] = step_operand(packed, o, int(threadIdx.x));
+}
+
+// Fused coarse D2Q9 step with the closure: pull, moments, features, MLP on the
+// matrix cores, a1^(2) += predicted correction, recursion and reconstruction,
+// store.  A block owns 64 columns of kClosureRows consecutive rows.  Wave w
+// pulls, and later collides, the 64 nodes of row y0 + w (one node per lane;
+// lanes past the row end, or on rows past the last, use a wrapped node and do
+// not store).  (rho - rho0, u) of the stored state on those rows and a
+// one-node halo go to LDS for the neighbour features.  Each wave then runs the
+// whole MLP for its own 64 samples, 16 at a time, with every weight and bias
+// in registers: a layer's products leave each lane four consecutive outputs of
+// one sample, which after the activation are the next layer's operand as they
+// stand (operand8_tiles orders the weights to match), so only the standardised
+// inputs and the three outputs pass through LDS.  The barriers wait for LDS
+// only: the pulled populations stay in flight until the collision.
 template <int N, class S>
 __global__ void __launch_bounds__(kClosureSamples)
     k_step_closure(const S* __restrict__ src, S* __restrict__ dst, StepArgs a, const uint16_t* __restrict__ packed,
                    const float* __restrict__ params, const float* __restrict__ norm) {
   using R = typename Prec<S>::R;
-  __shared__ __attribute__((aligned(16))) uint16_t r0[kClosureSamples * kLdH];
-  __shared__ __attribute__((aligned(16))) uint16_t r1[kClosureSamples * kLdH];
+  // standardised BF16 inputs; the padding keeps the operand reads of k 48 .. 63 (set to zero) of the last row inside
+  __shared__ __attribute__((aligned(16))) uint16_t xs[kClosureSamples * kLd1 + 16];
+  __shared__ __attribute__((aligned(16))) float ys[kClosureSamples][4];            // network outputs
   __shared__ __attribute__((aligned(16))) float cst[kNNorm];  // x_mean, 1 / x_std, y_mean, y_std
   __shared__ __attribute__((aligned(16))) float nb[kClosureRows + 2][66][4];  // (rho - rho0, u_x, u_y, -)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, l16 = lane & 15;
@@ -604,9 +604,9 @@ __global__ void __launch_bounds__(kClosureSamples)
   const bool active = xr < a.nx && yr < a.ny;
   const int x = xr < a.nx ? xr : xr % a.nx, y = yr < a.ny ? yr : yr % a.ny;
   // global loads first: one normalisation constant per thread, the lane's
-  // pulled populations, the stored populations of the halo nodes, the wave's
-  // weight slabs and its bias values (consumed in this order, so that no wait
-  // for one load waits for a later one)
+  // pulled populations, the stored populations of the halo nodes, then the
+  // weight operands and biases (consumed in this order, so that no wait for
+  // one load waits for a later one; at most 56 loads in flight per wave)
   const float nv = threadIdx.x < kNNorm ? norm[threadIdx.x] : 0.0f;
   R f[9];
   pull9<S, R>(src, a, x, y, f);
@@ -620,18 +620,23 @@ __global__ void __launch_bounds__(kClosureSamples)
       sfor<0, 9>([&](auto I) { p[h][I] = R(src[int64_t(I) * a.si + off]); });
     }
   }
-  const int j0 = 16 * wave;
-  const bf16x4* pw = reinterpret_cast<const bf16x4*>(packed);
-  bf16x4 w1[kInP / 16], w2[kH / 16], w3[kH / 16];
+  // A operands (rows: output features 16 jt + l16) from the register image,
+  // one 16-byte load each, and the biases that start the accumulators
+  const bf16x8* img = reinterpret_cast<const bf16x8*>(packed + kNPacked) + lane;
+  bf16x8 w1[4][2], w2[4][2], w3[2];
+  f32x4 b1[4], b2[4];
 #pragma unroll
-  for (int c = 0; c < kInP / 16; ++c) w1[c] = pw[(kPW1 + (j0 + l16) * kLd1 + 4 * q + 16 * c) / 4];
+  for (int jt = 0; jt < 4; ++jt) {
 #pragma unroll
-  for (int c = 0; c < kH / 16; ++c) {
-    w2[c] = pw[(kPW2 + (j0 + l16) * kLdH + 4 * q + 16 * c) / 4];
-    w3[c] = pw[(kPW3 + l16 * kLdH + 4 * q + 16 * c) / 4];
+    for (int c = 0; c < 2; ++c) {
+      w1[jt][c] = img[(2 * jt + c) * 64];
+      w2[jt][c] = img[(8 + 2 * jt + c) * 64];
+    }
+    b1[jt] = *reinterpret_cast<const f32x4*>(params + kOffB1 + 16 * jt + 4 * q);
+    b2[jt] = *reinterpret_cast<const f32x4*>(params + kOffB2 + 16 * jt + 4 * q);
   }
-  const f32x4 b1 = *reinterpret_cast<const f32x4*>(params + kOffB1 + j0 + 4 * q);
-  const f32x4 b2 = *reinterpret_cast<const f32x4*>(params + kOffB2 + j0 + 4 * q);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) w3[c] = img[(16 + c) * 64];
   const f32x4 b3 = q == 0 ? f32x4{params[kOffB3], params[kOffB3 + 1], params[kOffB3 + 2], 0.0f} : f32x4{0, 0, 0, 0};
   if (threadIdx.x < kNNorm) cst[threadIdx.x] = (threadIdx.x >= kIn && threadIdx.x < 2 * kIn) ? 1.0f / nv : nv;
   // halo moments -> LDS
@@ -645,7 +650,7 @@ __global__ void __launch_bounds__(kClosureSamples)
     }
   }
   lds_barrier();
-  // features of the lane's node -> its row of r0
+  // features of the lane's node -> its row of xs
   {
     float feat[kIn];
 #pragma unroll
@@ -658,39 +663,38 @@ __global__ void __launch_bounds__(kClosureSamples)
 #pragma unroll
         for (int c = 0; c < 3; ++c) feat[9 + 3 * (3 * dy + dx) + c] = v[c];
       }
-    write_features(feat, cst, cst + kIn, r0 + threadIdx.x * kLd1);
+    write_features(feat, cst, cst + kIn, xs + threadIdx.x * kLd1);
   }
   lds_barrier();
-  // layer 1: H1 = gelu(W1 X + b1), features j0 .. j0 + 15 of every sample -> r1
-  hidden_layer<kInP / 16, kClosureSamples / 16>(w1, b1, r0, kLd1, r1, j0);
-  lds_barrier();
-  // layer 2: H2 = gelu(W2 H1 + b2) -> r0
-  hidden_layer<kH / 16, kClosureSamples / 16>(w2, b2, r1, kLdH, r0, j0);
-  lds_barrier();
-  // layer 3: Y = W3 H2 + b3 for the wave's own samples, FP32 -> r1 as [sample][4]
-  float* ys = reinterpret_cast<float*>(r1);
-  {
-    // four independent tiles, their products interleaved so that no product waits for the previous one
-    bf16x4 hv[4][kH / 16];
-    f32x4 acc[4];
+  // the MLP of the wave's samples, 16 at a time (tile st: samples 64 wave + 16 st + l16)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const bf16x4* hb = reinterpret_cast<const bf16x4*>(r0 + (64 * wave + 16 * t + l16) * kLdH + 4 * q);
+  for (int st = 0; st < 4; ++st) {
+    const uint16_t* xrow = xs + (64 * wave + 16 * st + l16) * kLd1;
+    const bf16x8 x1[2] = {operand8(xrow, 0, q, kInP), operand8(xrow, 1, q, kInP)};
+    bf16x4 h[4];
 #pragma unroll
-      for (int c = 0; c < kH / 16; ++c) hv[t][c] = hb[4 * c];
-      acc[t] = b3;
+    for (int jt = 0; jt < 4; ++jt) {  // H1 = gelu(W1 X + b1)
+      f32x4 acc = b1[jt];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[jt][c], x1[c], acc, 0, 0, 0);
+      h[jt] = pack_bf16(gelu(acc[0]), gelu(acc[1]), gelu(acc[2]), gelu(acc[3]));
     }
+    const bf16x8 x2[2] = {join8(h[0], h[1]), join8(h[2], h[3])};
 #pragma unroll
-    for (int c = 0; c < kH / 16; ++c)
+    for (int jt = 0; jt < 4; ++jt) {  // H2 = gelu(W2 H1 + b2)
+      f32x4 acc = b2[jt];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w3[c], hv[t][c], acc[t], 0, 0, 0);
-    if (q == 0) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) *reinterpret_cast<f32x4*>(ys + (64 * wave + 16 * t + l16) * 4) = acc[t];
+      for (int c = 0; c < 2; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[jt][c], x2[c], acc, 0, 0, 0);
+      h[jt] = pack_bf16(gelu(acc[0]), gelu(acc[1]), gelu(acc[2]), gelu(acc[3]));
     }
+    const bf16x8 x3[2] = {join8(h[0], h[1]), join8(h[2], h[3])};
+    f32x4 acc = b3;  // Y = W3 H2 + b3: rows 0..2 of the tile, in lanes 0..15
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[c], x3[c], acc, 0, 0, 0);
+    if (q == 0) *reinterpret_cast<f32x4*>(&ys[64 * wave + 16 * st + l16][0]) = acc;
   }
   lds_barrier();
-  const f32x4 yv = *reinterpret_cast<const f32x4*>(ys + threadIdx.x * 4);
+  const f32x4 yv = *reinterpret_cast<const f32x4*>(&ys[threadIdx.x][0]);
   const Moments<R> mo = raw_moments<D2Q9, R>(f);
   Hydro<R> h = hydro<D2Q9, R>(mo, R(a.rho0));
   const float* ym = cst + 2 * kIn;
@@ -782,6 +786,13 @@ hipError_t closure_coarsen(int dtype, const void* rho, const void* u, const void
 
 hipError_t mlp_pack(const float* params, uint16_t* packed, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3((kNPacked + 255) / 256), dim3(256), 0, s, params, packed);
+  return hipGetLastError();
+}
+
+hipError_t mlp_pack_step(const float* params, uint16_t* packed_and_image, hipStream_t s) {
+  if (hipError_t e = mlp_pack(params, packed_and_image, s); e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pack_image, dim3(kNOps), dim3(64), 0, s, packed_and_image,
+                     reinterpret_cast<bf16x8*>(packed_and_image + kNPacked));
   return hipGetLastError();
 }
 
