@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdint>
 
 #include "closure.hpp"
@@ -587,21 +588,25 @@ __global__ void __launch_bounds__(64) k_pack_image(const uint16_t* __restrict__ 
 // stand (operand8_tiles orders the weights to match), so only the standardised
 // inputs and the three outputs pass through LDS.  The barriers wait for LDS
 // only: the pulled populations stay in flight until the collision.
-template <int N, class S>
-__global__ void __launch_bounds__(kClosureSamples)
+template <int N, class S, int WPR>
+__global__ void __launch_bounds__(kClosureSamples * WPR)
     k_step_closure(const S* __restrict__ src, S* __restrict__ dst, StepArgs a, const uint16_t* __restrict__ packed,
                    const float* __restrict__ params, const float* __restrict__ norm) {
   using R = typename Prec<S>::R;
+  constexpr int kThreads = kClosureSamples * WPR, kTiles = 4 / WPR;  // sample tiles of 16 per wave
   // standardised BF16 inputs; the padding keeps the operand reads of k 48 .. 63 (set to zero) of the last row inside
   __shared__ __attribute__((aligned(16))) uint16_t xs[kClosureSamples * kLd1 + 16];
   __shared__ __attribute__((aligned(16))) float ys[kClosureSamples][4];            // network outputs
   __shared__ __attribute__((aligned(16))) float cst[kNNorm];  // x_mean, 1 / x_std, y_mean, y_std
   __shared__ __attribute__((aligned(16))) float nb[kClosureRows + 2][66][4];  // (rho - rho0, u_x, u_y, -)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, l16 = lane & 15;
+  // the row's waves share its 64 samples (one wave per row: row = wave, part 0)
+  const int row = WPR == 1 ? wave : wave % kClosureRows, part = WPR == 1 ? 0 : wave / kClosureRows;
+  const bool owner = part == 0;  // the wave that pulls and collides the row
   const int gx = (a.nx + 63) / 64;
   const int x0 = int(blockIdx.x % unsigned(gx)) * 64, y0 = int(blockIdx.x / unsigned(gx)) * kClosureRows;
-  const int xr = x0 + lane, yr = y0 + wave;
-  const bool active = xr < a.nx && yr < a.ny;
+  const int xr = x0 + lane, yr = y0 + row;
+  const bool active = owner && xr < a.nx && yr < a.ny;
   const int x = xr < a.nx ? xr : xr % a.nx, y = yr < a.ny ? yr : yr % a.ny;
   // global loads first: one normalisation constant per thread, the lane's
   // pulled populations, the stored populations of the halo nodes, then the
@@ -609,12 +614,12 @@ __global__ void __launch_bounds__(kClosureSamples)
   // one load waits for a later one; at most 56 loads in flight per wave)
   const float nv = threadIdx.x < kNNorm ? norm[threadIdx.x] : 0.0f;
   R f[9];
-  pull9<S, R>(src, a, x, y, f);
-  constexpr int kPer = (kClosureHalo + kClosureSamples - 1) / kClosureSamples;
+  if (owner) pull9<S, R>(src, a, x, y, f);
+  constexpr int kPer = (kClosureHalo + kThreads - 1) / kThreads;
   R p[kPer][9];
 #pragma unroll
   for (int h = 0; h < kPer; ++h) {
-    const int k = int(threadIdx.x) + h * kClosureSamples;
+    const int k = int(threadIdx.x) + h * kThreads;
     if (k < kClosureHalo) {
       const int64_t off = int64_t(wrap(y0 - 1 + k / 66, a.ny)) * a.sy + wrap(x0 - 1 + k % 66, a.nx);
       sfor<0, 9>([&](auto I) { p[h][I] = R(src[int64_t(I) * a.si + off]); });
@@ -642,7 +647,7 @@ __global__ void __launch_bounds__(kClosureSamples)
   // halo moments -> LDS
 #pragma unroll
   for (int h = 0; h < kPer; ++h) {
-    const int k = int(threadIdx.x) + h * kClosureSamples;
+    const int k = int(threadIdx.x) + h * kThreads;
     if (k < kClosureHalo) {
       const Moments<R> mo = raw_moments<D2Q9, R>(p[h]);
       const Hydro<R> hh = hydro<D2Q9, R>(mo, R(a.rho0));
@@ -651,7 +656,7 @@ __global__ void __launch_bounds__(kClosureSamples)
   }
   lds_barrier();
   // features of the lane's node -> its row of xs
-  {
+  if (owner) {
     float feat[kIn];
 #pragma unroll
     for (int i = 0; i < 9; ++i) feat[i] = float(f[i]);
@@ -659,17 +664,18 @@ __global__ void __launch_bounds__(kClosureSamples)
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
-        const f32x4 v = *reinterpret_cast<const f32x4*>(&nb[wave + dy][lane + dx][0]);
+        const f32x4 v = *reinterpret_cast<const f32x4*>(&nb[row + dy][lane + dx][0]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) feat[9 + 3 * (3 * dy + dx) + c] = v[c];
       }
-    write_features(feat, cst, cst + kIn, xs + threadIdx.x * kLd1);
+    write_features(feat, cst, cst + kIn, xs + (64 * row + lane) * kLd1);
   }
   lds_barrier();
-  // the MLP of the wave's samples, 16 at a time (tile st: samples 64 wave + 16 st + l16)
+  // the MLP of the wave's samples, 16 at a time (tile st: samples 64 row + 16 st + l16)
 #pragma unroll
-  for (int st = 0; st < 4; ++st) {
-    const uint16_t* xrow = xs + (64 * wave + 16 * st + l16) * kLd1;
+  for (int t = 0; t < kTiles; ++t) {
+    const int st = part * kTiles + t;
+    const uint16_t* xrow = xs + (64 * row + 16 * st + l16) * kLd1;
     const bf16x8 x1[2] = {operand8(xrow, 0, q, kInP), operand8(xrow, 1, q, kInP)};
     bf16x4 h[4];
 #pragma unroll
@@ -691,10 +697,11 @@ __global__ void __launch_bounds__(kClosureSamples)
     f32x4 acc = b3;  // Y = W3 H2 + b3: rows 0..2 of the tile, in lanes 0..15
 #pragma unroll
     for (int c = 0; c < 2; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3[c], x3[c], acc, 0, 0, 0);
-    if (q == 0) *reinterpret_cast<f32x4*>(&ys[64 * wave + 16 * st + l16][0]) = acc;
+    if (q == 0) *reinterpret_cast<f32x4*>(&ys[64 * row + 16 * st + l16][0]) = acc;
   }
   lds_barrier();
-  const f32x4 yv = *reinterpret_cast<const f32x4*>(&ys[threadIdx.x][0]);
+  if (!owner) return;
+  const f32x4 yv = *reinterpret_cast<const f32x4*>(&ys[64 * row + lane][0]);
   const Moments<R> mo = raw_moments<D2Q9, R>(f);
   Hydro<R> h = hydro<D2Q9, R>(mo, R(a.rho0));
   const float* ym = cst + 2 * kIn;
@@ -711,29 +718,45 @@ __global__ void __launch_bounds__(kClosureSamples)
   }
 }
 
+template <class S, int WPR>
+hipError_t launch_closure(int order, dim3 grid, const void* src, void* dst, const StepArgs& a, const uint16_t* packed,
+                          const float* params, const float* norm, hipStream_t s) {
+  const dim3 block(kClosureSamples * WPR);
+  switch (order) {
+    case 2:
+      hipLaunchKernelGGL((k_step_closure<2, S, WPR>), grid, block, 0, s, static_cast<const S*>(src),
+                         static_cast<S*>(dst), a, packed, params, norm);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_step_closure<3, S, WPR>), grid, block, 0, s, static_cast<const S*>(src),
+                         static_cast<S*>(dst), a, packed, params, norm);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_step_closure<4, S, WPR>), grid, block, 0, s, static_cast<const S*>(src),
+                         static_cast<S*>(dst), a, packed, params, norm);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <class S>
 hipError_t step_closure_s(int order, const void* src, void* dst, const StepArgs& a, const uint16_t* packed,
                           const float* params, const float* norm, hipStream_t s) {
   const int64_t blocks = int64_t((a.nx + 63) / 64) * ((a.ny + kClosureRows - 1) / kClosureRows);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  dim3 grid(unsigned(blocks), 1, 1);
-  const int bx = kClosureSamples;
-  switch (order) {
-    case 2:
-      hipLaunchKernelGGL((k_step_closure<2, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
-                         a, packed, params, norm);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_step_closure<3, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
-                         a, packed, params, norm);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_step_closure<4, S>), grid, dim3(bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
-                         a, packed, params, norm);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  const dim3 grid = dim3(unsigned(blocks));
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  // grids that give at most one block per compute unit leave one wave per SIMD: two waves per row there
+  // (FP64 storage keeps one: two would spill)
+  const char* e = std::getenv("LBRR_CLOSURE_WPR");
+  const int wpr = sizeof(S) == 8 ? 1 : (e ? std::atoi(e) : (blocks <= cus ? 2 : 1));
+  if constexpr (sizeof(S) == 8) return launch_closure<S, 1>(order, grid, src, dst, a, packed, params, norm, s);
+  else
+    return wpr == 2 ? launch_closure<S, 2>(order, grid, src, dst, a, packed, params, norm, s)
+                    : launch_closure<S, 1>(order, grid, src, dst, a, packed, params, norm, s);
 }
 
 template <class S>

@@ -163,17 +163,21 @@ def _oracle_closure_step(g, params, norm, tau):
     return rr.reconstruct(L, 4, a0 + (1 - 1 / tau) * a1), d
 
 
+@pytest.mark.parametrize("wpr", ["1", "2"])
 @pytest.mark.parametrize("storage", ["fp64", "fp32", "fp16"])
 @pytest.mark.parametrize("ny,nx", [(24, 200), (25, 130), (3, 10), (1, 70)])
-def test_fused_closure_step(lbrr, gpu, storage, ny, nx):
+def test_fused_closure_step(lbrr, gpu, storage, ny, nx, wpr, monkeypatch):
     """Rows of 4 and 3 tiles of 64 columns with ragged ends; the fused step's blocks cover 4 rows,
     so at ny = 25 the last block row holds one row of the grid and three past it.  The tiny
     periodic boxes (3 x 10, 1 x 70) wrap the neighbour halo several times over.  Three more
-    steps check the state carried from one closure step to the next.
+    steps check the state carried from one closure step to the next.  Both launch forms of the
+    fused step: one wave per row and two (the form the library takes on grids of at most one
+    block per compute unit; FP64 storage always takes one).
 
     FP16 storage: the oracle starts from the FP16-rounded deviations the library stores, and the
     bar adds one FP16 rounding of the stored outputs (2^-11 of the largest deviation)."""
     torch = gpu
+    monkeypatch.setenv("LBRR_CLOSURE_WPR", wpr)
     L = OL.lattice("D2Q9")
     tau = 0.58
     rho, u, pi1 = (1.0 + W.smooth_random(1, (1, ny, nx), 0.02, 31)[0], W.smooth_random(2, (1, ny, nx), 0.06, 32),
