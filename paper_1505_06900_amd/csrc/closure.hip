@@ -577,15 +577,17 @@ __global__ void __launch_bounds__(64) k_pack_image(const uint16_t* __restrict__ 
 
 // Fused coarse D2Q9 step with the closure: pull, moments, features, MLP on the
 // matrix cores, a1^(2) += predicted correction, recursion and reconstruction,
-// store.  A block owns 64 columns of kClosureRows consecutive rows.  Wave w
-// pulls, and later collides, the 64 nodes of row y0 + w (one node per lane;
-// lanes past the row end, or on rows past the last, use a wrapped node and do
-// not store).  (rho - rho0, u) of the stored state on those rows and a
-// one-node halo go to LDS for the neighbour features.  Each wave then runs the
-// whole MLP for its own 64 samples, 16 at a time, with every weight and bias
-// in registers: a layer's products leave each lane four consecutive outputs of
-// one sample, which after the activation are the next layer's operand as they
-// stand (operand8_tiles orders the weights to match), so only the standardised
+// store.  A block owns 64 columns of kClosureRows consecutive rows and has WPR
+// waves per row.  The row's first wave (w < kClosureRows, row y0 + w) pulls,
+// and later collides, its 64 nodes (one node per lane; lanes past the row end,
+// or on rows past the last, use a wrapped node and do not store).
+// (rho - rho0, u) of the stored state on those rows and a one-node halo go to
+// LDS for the neighbour features.  The row's WPR waves then share the MLP of
+// its 64 samples, 16 at a time (its wave p = w / kClosureRows takes the 4 / WPR
+// tiles from p (4 / WPR) on), with every weight and bias in registers: a
+// layer's products leave each lane four consecutive outputs of one sample,
+// which after the activation are the next layer's operand as they stand
+// (operand8_tiles orders the weights to match), so only the standardised
 // inputs and the three outputs pass through LDS.  The barriers wait for LDS
 // only: the pulled populations stay in flight until the collision.
 template <int N, class S, int WPR>
