@@ -40,6 +40,18 @@
  *    With moment storage they hold the pre-collision moments (lb_config).
  *  - All device work is enqueued on the handle's stream (default: the null
  *    stream).  Entry points that return host data synchronise that stream.
+ *  - Tuning overrides (environment variables; the defaults are the choices
+ *    measured fastest on MI355X).  They change where data lives or how work
+ *    is launched, not what is computed; a value out of range is ignored.
+ *      LBRR_LAYOUT=0|1|2        state layout, read when a handle's buffers
+ *                               are allocated: 0 [q][z][y][x], 1 [z][y][q][x],
+ *                               2 [z][q][y][x] (q: population or field)
+ *      LBRR_PLANE_PAD_BYTES=n   bytes after each population plane in layouts
+ *                               0 and 2, rounded up to 256 (read at allocation)
+ *      LBRR_MOM_LZ=n            z-planes (3D) or rows (2D) per block of the
+ *                               moment-storage step, n >= 1 (read every step)
+ *      LBRR_CLOSURE_WPR=1|2     waves per row of the fused closure step with
+ *                               FP32 or FP16 storage (read every step)
  */
 #ifndef LBRR_H
 #define LBRR_H

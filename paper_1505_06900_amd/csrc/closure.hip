@@ -748,17 +748,22 @@ hipError_t step_closure_s(int order, const void* src, void* dst, const StepArgs&
   const int64_t blocks = int64_t((a.nx + 63) / 64) * ((a.ny + kClosureRows - 1) / kClosureRows);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid = dim3(unsigned(blocks));
-  int cus = 256;
-  int dev = 0;
-  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  // grids that give at most one block per compute unit leave one wave per SIMD: two waves per row there
-  // (FP64 storage keeps one: two would spill)
-  const char* e = std::getenv("LBRR_CLOSURE_WPR");
-  const int wpr = sizeof(S) == 8 ? 1 : (e ? std::atoi(e) : (blocks <= cus ? 2 : 1));
-  if constexpr (sizeof(S) == 8) return launch_closure<S, 1>(order, grid, src, dst, a, packed, params, norm, s);
-  else
+  if constexpr (sizeof(S) == 8) {  // FP64 storage keeps one wave per row: two would spill
+    return launch_closure<S, 1>(order, grid, src, dst, a, packed, params, norm, s);
+  } else {
+    // grids that give at most one block per compute unit leave one wave per SIMD: two waves per row there
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int wpr = blocks <= cus ? 2 : 1;
+    if (const char* e = std::getenv("LBRR_CLOSURE_WPR")) {  // 1 or 2; other values are ignored
+      const int v = std::atoi(e);
+      if (v == 1 || v == 2) wpr = v;
+    }
     return wpr == 2 ? launch_closure<S, 2>(order, grid, src, dst, a, packed, params, norm, s)
                     : launch_closure<S, 1>(order, grid, src, dst, a, packed, params, norm, s);
+  }
 }
 
 template <class S>
