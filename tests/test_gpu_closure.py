@@ -226,3 +226,33 @@ def test_fused_closure_step(lbrr, gpu, storage, ny, nx, wpr, monkeypatch):
     assert err4 <= 4 * (2e-3 * effect + store)
     plain.close()
     clos.close()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+@pytest.mark.parametrize("ny,nx", [(25, 130), (64, 64)])
+def test_fused_closure_launch_forms_agree_bitwise(lbrr, gpu, storage, ny, nx, monkeypatch):
+    """The two launch forms of the fused step (one and two waves per row) compute every
+    sample's features, products and activations in the same order, so five steps from the
+    same state give the same bits; an out-of-range LBRR_CLOSURE_WPR is ignored (the
+    library's own choice, also the same bits)."""
+    torch = gpu
+    L = OL.lattice("D2Q9")
+    tau = 0.55
+    rho, u = 1.0 + W.smooth_random(1, (1, ny, nx), 0.02, 41)[0], W.smooth_random(2, (1, ny, nx), 0.06, 42)
+    g = rr.init_populations(L, 4, rho, u)
+    wr = L.w[:, None, None, None]
+    rng = np.random.default_rng(43)
+    params = OM.init_params(44) + 0.05 * rng.standard_normal(OM.NPARAM).astype(np.float32)
+    norm = rand_norm(rng, scale_y=2e-4)
+    out = {}
+    for wpr in ("1", "2", "7"):
+        monkeypatch.setenv("LBRR_CLOSURE_WPR", wpr)
+        sim = lbrr.Simulation("D2Q9", (1, ny, nx), tau, 4, storage=storage)
+        sim.set_populations(torch.from_numpy(g - wr))
+        sim.set_closure(torch.from_numpy(params), torch.from_numpy(norm))
+        sim.step(5)
+        out[wpr] = sim.get_populations().cpu().numpy()
+        sim.close()
+    assert np.isfinite(out["1"]).all()
+    assert np.array_equal(out["1"], out["2"])
+    assert np.array_equal(out["1"], out["7"])
