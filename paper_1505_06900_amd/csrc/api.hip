@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "closure.hpp"
 #include "lbrr.h"
@@ -702,12 +703,18 @@ int lb_set_closure(lb_handle h, const float* params, const float* norm, int enab
     return LB_OK;
   }
   if (!params || !norm) return fail(LB_ERR_INVALID_ARG, "params and norm must not be NULL");
-  if (!h->cl_params) {
-    HIP_TRY(hipMalloc(&h->cl_params, sizeof(float) * lbrr::kMlpNParam), "hipMalloc closure params");
-    HIP_TRY(hipMalloc(&h->cl_norm, sizeof(float) * lbrr::kMlpNNorm), "hipMalloc closure norm");
-    HIP_TRY(hipMalloc(&h->cl_packed, sizeof(uint16_t) * (lbrr::kMlpNPacked + lbrr::kMlpNRegImage)),
-            "hipMalloc closure weights");
-  }
+  // each buffer on its own, through a temporary: after a failed allocation the
+  // handle holds only complete buffers, and the next call allocates the rest
+  auto alloc = [](auto*& dst, size_t bytes) {
+    void* p = nullptr;
+    const hipError_t e = dst ? hipSuccess : hipMalloc(&p, bytes);
+    if (e == hipSuccess && !dst) dst = static_cast<std::remove_reference_t<decltype(dst)>>(p);
+    return e;
+  };
+  HIP_TRY(alloc(h->cl_params, sizeof(float) * lbrr::kMlpNParam), "hipMalloc closure params");
+  HIP_TRY(alloc(h->cl_norm, sizeof(float) * lbrr::kMlpNNorm), "hipMalloc closure norm");
+  HIP_TRY(alloc(h->cl_packed, sizeof(uint16_t) * (lbrr::kMlpNPacked + lbrr::kMlpNRegImage)),
+          "hipMalloc closure weights");
   HIP_TRY(hipMemcpyAsync(h->cl_params, params, sizeof(float) * lbrr::kMlpNParam, hipMemcpyDeviceToDevice, h->stream),
           "copy closure params");
   HIP_TRY(hipMemcpyAsync(h->cl_norm, norm, sizeof(float) * lbrr::kMlpNNorm, hipMemcpyDeviceToDevice, h->stream),
