@@ -131,7 +131,11 @@ int lb_init_fields(lb_handle h, const void* rho, const void* u, const void* pi1,
  * check interval is set (lb_set_check_interval), in which case the density
  * and velocity are checked every k steps and LB_ERR_UNSTABLE is returned
  * after the first check that finds a non-finite value (the state then holds
- * the failing step). */
+ * the failing step).  Without a check interval the call only launches
+ * kernels (no allocation, memset or synchronisation), so it can be captured
+ * in a HIP graph on the handle's stream.  Each step swaps the handle's two
+ * state buffers: replays of a captured run keep the handle's bookkeeping
+ * right only if n is even. */
 int lb_step(lb_handle h, long long n);
 
 /* Resting no-slip walls (u = 0) on the first and last node of each axis in
