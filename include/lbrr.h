@@ -52,6 +52,8 @@
  *                               moment-storage step, n >= 1 (read every step)
  *      LBRR_CLOSURE_WPR=1|2     waves per row of the fused closure step with
  *                               FP32 or FP16 storage (read every step)
+ *      LBRR_STEP_BLOCKS_PER_CU=n  blocks of the population step per compute
+ *                               unit, 1..8, 0 for no limit (read every step)
  */
 #ifndef LBRR_H
 #define LBRR_H

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 
 #include "collide.hpp"
 #include "ops.hpp"
@@ -381,11 +382,44 @@ inline hipError_t step_grid(const StepArgs& a, dim3& grid, dim3& block) {
   return (grid.y > 65535u || grid.z > 65535u) ? hipErrorInvalidValue : hipSuccess;
 }
 
+// Blocks of the population step per compute unit, limited by reserving LDS
+// that the kernel does not use (0: no limit, eight 256-thread blocks, eight
+// waves per SIMD).  Measured on MI355X, one run, interleaved (GLUPS, default
+// -> six blocks): D3Q27 FP16 512^3 50.2 -> 54.0, 256^3 54.4 -> 55.8; FP64
+// 512^3 11.8 -> 12.1, 256^3 unchanged.  D3Q27 FP32 gains nothing, and D3Q19
+// FP16 (71.1 -> 69.3) and D2Q9 FP16 (151 -> 138) lose, so they keep every
+// block.  With 27 streams of 2- or 8-byte lanes, fewer waves in flight keep
+// fewer DRAM pages open at once.  LBRR_STEP_BLOCKS_PER_CU=0..8 overrides.
+template <class L, class S>
+int step_blocks_per_cu() {
+  int blocks = (L::Q == 27 && sizeof(S) != 4) ? 6 : 0;
+  if (const char* e = std::getenv("LBRR_STEP_BLOCKS_PER_CU")) {
+    const int v = std::atoi(e);
+    if (v >= 0 && v <= 8) blocks = v;
+  }
+  return blocks;
+}
+
+// Dynamic LDS bytes per block that leave room for at most `blocks` blocks per
+// compute unit (a multiple of 2 KiB, so the count does not depend on the
+// allocation granularity); 0 when there is no limit or the device is unknown.
+inline unsigned lds_reserve(int blocks) {
+  if (blocks <= 0) return 0u;
+  int dev = 0, per_cu = 0, per_block = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 0u;
+  const int r = per_cu / blocks / 2048 * 2048;
+  return unsigned(r < per_block ? r : per_block);
+}
+
 template <class L, int N, class S>
 hipError_t launch_step(const void* src, void* dst, const StepArgs& a, hipStream_t s) {
   dim3 grid, block;
   if (step_grid(a, grid, block) != hipSuccess) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_step<L, N, S>), grid, block, 0, s, static_cast<const S*>(src), static_cast<S*>(dst), a);
+  const unsigned lds = lds_reserve(step_blocks_per_cu<L, S>());
+  hipLaunchKernelGGL((k_step<L, N, S>), grid, block, lds, s, static_cast<const S*>(src), static_cast<S*>(dst), a);
   return hipGetLastError();
 }
 
