@@ -11,7 +11,9 @@ check, host-memory arguments and streams other than the default one.
   lb_get/set_populations gives the same bits as device memory;
 * a non-default torch stream, and a switch of stream between steps
   (lb_set_stream orders the new stream after the work on the old one), give the
-  same bits as the default stream.
+  same bits as the default stream;
+* poisoned destination: a step into a state buffer full of NaN writes every
+  entry (plain, walled and closure steps).
 """
 import ctypes
 
@@ -169,3 +171,58 @@ def test_non_default_stream_and_stream_switch(lbrr, gpu, storage):
     sim.close()
     torch.cuda.synchronize()
     assert np.array_equal(got, want)
+
+
+def _poison_cases():
+    out = []
+    for lat, shape, N in CASES:
+        for storage in ("fp64", "fp32", "fp16"):
+            for variant in ("plain", "walls") + (("closure",) if lat == "D2Q9" else ()):
+                out.append(pytest.param(lat, shape, N, storage, variant, id=f"{lat}-{storage}-{variant}"))
+    return out
+
+
+@pytest.mark.parametrize("lat,shape,N,storage,variant", _poison_cases())
+def test_every_destination_entry_is_written(lbrr, gpu, lat, shape, N, storage, variant):
+    """Poisoned destination: a step into a state buffer full of NaN leaves no NaN behind.
+
+    NaN populations and one step put NaN into both of the handle's state buffers;
+    lb_set_populations then overwrites the current one with a valid state, and the
+    next step writes into the poisoned one.  Every stored entry must come out finite
+    and equal, bit for bit, to the same step on a fresh handle (plain step, the
+    step with resting walls on every axis, and the fused closure step)."""
+    torch = gpu
+    from oracle import mlp as OM
+
+    D = 2 if lat == "D2Q9" else 3
+    rho, u, pi1 = fields(D, shape, 71)
+    rng = np.random.default_rng(72)
+    params = torch.from_numpy(OM.init_params(73) + 0.05 * rng.standard_normal(OM.NPARAM).astype(np.float32))
+    norm = torch.from_numpy(np.concatenate([0.01 * rng.standard_normal(36), 0.02 * (1 + rng.uniform(size=36)),
+                                            1e-5 * rng.standard_normal(3), 1e-4 * (1 + rng.uniform(size=3))])
+                            .astype(np.float32))
+
+    def configure(sim):
+        if variant == "walls":
+            sim.set_walls(x=True, y=True, z=D == 3)
+        if variant == "closure":
+            sim.set_closure(params, norm)
+
+    ref = lbrr.Simulation(lat, shape, 0.57, N, storage=storage)
+    ref.init_fields(rho, u, pi1)
+    configure(ref)
+    state = ref.get_populations()
+    ref.step(1)
+    want = populations(ref)
+    sim = lbrr.Simulation(lat, shape, 0.57, N, storage=storage)
+    configure(sim)
+    sim.set_populations(torch.full_like(state, float("nan")))
+    sim.step(1)
+    assert np.isnan(populations(sim)).all()  # both buffers poisoned
+    sim.set_populations(state)
+    sim.step(1)
+    got = populations(sim)
+    assert np.isfinite(got).all()
+    assert np.array_equal(got, want)
+    ref.close()
+    sim.close()
