@@ -1,6 +1,11 @@
 """Build the HIP library liblbrr.so in-tree for gfx950 (hipcc, no GPU needed).
 
-Usage: python -m paper_1505_06900_amd.build [-j JOBS] [--verbose]
+Usage: python -m paper_1505_06900_amd.build [-j JOBS] [--verbose] [--sanitized DIR]
+
+--sanitized DIR also writes DIR/liblbrr_asan.so: the same library with its host
+code built with AddressSanitizer and UndefinedBehaviorSanitizer (the GPU code is
+the normal build's, taken from its objects), for host-side tests on the CPU with
+the sanitizer runtime preloaded (sanitizer_runtime()).
 """
 from __future__ import annotations
 
@@ -109,12 +114,71 @@ def build(jobs=None, verbose=False):
     return LIB
 
 
+def _llvm_tool(name):
+    exe = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "llvm", "bin", name)
+    exe = exe if os.path.exists(exe) else os.path.join("/opt/rocm/llvm/bin", name)
+    if not os.path.exists(exe):
+        raise RuntimeError(f"{name} not found")
+    return exe
+
+
+def sanitizer_runtime():
+    """Path of the AddressSanitizer runtime of the ROCm compiler (it carries the UBSan handlers), or None."""
+    import glob
+
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    return hits[-1] if hits else None
+
+
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(out_dir, jobs=None):
+    """Host code under ASan + UBSan, GPU code from the normal build's objects (build() first).
+
+    Each source's host part is compiled alone (--offload-host-only) with the GPU
+    binary that build() embedded in its object passed back in, so the GPU code is
+    not compiled again."""
+    os.makedirs(out_dir, exist_ok=True)
+    objcopy = _llvm_tool("llvm-objcopy")
+
+    def one(src):
+        stem = os.path.splitext(src)[0]
+        normal = os.path.join(BUILD, stem + ".o")
+        if not os.path.exists(normal):
+            raise RuntimeError(f"{normal} is missing: run build() first")
+        fatbin = os.path.join(out_dir, stem + ".fatbin")
+        subprocess.run([objcopy, "-O", "binary", "--only-section=.hip_fatbin", normal, fatbin], check=True)
+        obj = os.path.join(out_dir, stem + ".o")
+        cmd = [hipcc(), f"--offload-arch={ARCH}", "--offload-host-only", "-Xclang", "-fcuda-include-gpubinary",
+               "-Xclang", fatbin, "-O1", "-g", "-std=c++17", "-fPIC", "-Wno-unused-command-line-argument", *SANITIZE,
+               "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"sanitized host compile failed for {src}:\n{r.stderr}")
+        return obj
+
+    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, SOURCES))
+    lib = os.path.join(out_dir, "liblbrr_asan.so")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "--offload-host-only", "-shared", "-fPIC", *objs, *SANITIZE, "-o", lib]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"sanitized link failed:\n{r.stderr}")
+    return lib
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", "--jobs", type=int, default=None)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--sanitized", metavar="DIR", default=None)
     a = ap.parse_args(argv)
     print(build(a.jobs, a.verbose))
+    if a.sanitized:
+        print(build_sanitized(a.sanitized, a.jobs))
 
 
 if __name__ == "__main__":
