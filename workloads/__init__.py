@@ -156,8 +156,8 @@ WORKLOADS = {
     "tgv3d_64_ma01": dict(lattice="D3Q27", order=4, n=64, u0=0.1 * CS, tau=0.501103, steps=2500),
     "tgv3d_64_ma05": dict(lattice="D3Q27", order=4, n=64, u0=0.5 * CS, tau=0.505513, steps=2500),
     # 512^3 random solenoidal field, |k| <= 8, rms Ma 0.1, tau = 0.51
-    # D3Q19 at order 3: at tau = 0.51 the order-4 D3Q19 model grows high-wavenumber modes even at
-    # rest (0.0285 per step, linear stability analysis of the oracle collision)
+    # D3Q19 at order 4 with f1 stopping at order 3, the reading that is stable at rest at this tau
+    # (with f1 at order 4 the model grew high-wavenumber modes at rest, 0.0285 per step)
     "solenoidal_512_d3q19": dict(lattice="D3Q19", order=4, n=512, kmax=8, urms=0.1 * CS, tau=0.51, steps=1000),
     "solenoidal_512_d3q27": dict(lattice="D3Q27", order=4, n=512, kmax=8, urms=0.1 * CS, tau=0.51, steps=1000),
     # decaying 2D turbulence for the learned closure: fine 1024^2, coarse 256^2 (dx_c = 4 dx_f)
