@@ -164,3 +164,24 @@ WORKLOADS = {
     "turb2d_fine_1024": dict(lattice="D2Q9", order=4, n=1024, kmin=4, kmax=12, urms=0.1 * CS, tau=0.535472),
     "turb2d_coarse_256": dict(lattice="D2Q9", order=4, n=256, tau=0.508868),
 }
+
+
+def initial_fields(name, seed=0):
+    """rho (nz,ny,nx) and u (d,nz,ny,nx) at t = 0 of the workload ``name`` of WORKLOADS, with the
+    box shape (nz, ny, nx); the same recipes the full-size tests use."""
+    cfg = WORKLOADS[name]
+    n = cfg["n"]
+    if name.startswith("tgv2d"):
+        rho, u = tgv2d(n, cfg["u0"])
+    elif name.startswith("shear"):
+        rho, u = shear_layer(n, cfg["u0"], seed)
+    elif name.startswith("tgv3d"):
+        rho, u = tgv3d(n, cfg["u0"])
+    elif name.startswith("solenoidal"):
+        rho, u = random_solenoidal3d(n, cfg["kmax"], cfg["urms"], seed)
+    elif name.startswith("turb2d_fine"):
+        rho, u = random_vorticity2d(n, cfg["kmin"], cfg["kmax"], cfg["urms"], seed)
+    else:
+        raise KeyError(f"{name} has no initial-field recipe of its own")
+    shape = (1, n, n) if cfg["lattice"] == "D2Q9" else (n, n, n)
+    return np.asarray(rho, dtype=np.float64).reshape(shape), np.asarray(u, dtype=np.float64).reshape((len(u),) + shape), shape
