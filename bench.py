@@ -237,8 +237,9 @@ def probe_table(P, torch, nbytes=2 << 30, reps=10):
     return rows
 
 
-def probe(P, torch, storages, steps=5):
-    """Short fixed launch sequence for hardware-counter runs: copies of known size, then step kernels."""
+def probe(P, torch, storages, steps=5, lattices=(("D3Q27", None),)):
+    """Short fixed launch sequence for hardware-counter runs: copies of known size, then step kernels
+    (each lattice and order of ``lattices``, order None = the workload's, every storage)."""
     import ctypes
 
     import workloads as W
@@ -254,14 +255,18 @@ def probe(P, torch, storages, steps=5):
     cfg = W.WORKLOADS[WORKLOAD]
     n = cfg["n"]
     rho, u = W.tgv3d(n, cfg["u0"])
-    for st in storages:
-        sim = P.Simulation("D3Q27", (n, n, n), cfg["tau"], cfg["order"], storage=st)
-        sim.init_fields(rho, u)
-        sim.step(steps)
-        torch.cuda.synchronize()
-        log(f"probe {st}: {steps} steps, {sim.bytes_per_update * n**3:.0f} algorithmic bytes per launch")
-        sim.close()
-    return {"copy_bytes": nbytes, "copies": 3, "storages": storages, "steps": steps, "nodes": n**3}
+    for lat, order in lattices:
+        order = order or cfg["order"]
+        for st in storages:
+            sim = P.Simulation(lat, (n, n, n), cfg["tau"], order, storage=st)
+            sim.init_fields(rho, u)
+            sim.step(steps)
+            torch.cuda.synchronize()
+            log(f"probe {lat} order {order} {st}: {steps} steps, "
+                f"{sim.bytes_per_update * n**3:.0f} algorithmic bytes per launch")
+            sim.close()
+    return {"copy_bytes": nbytes, "copies": 3, "storages": storages, "steps": steps, "nodes": n**3,
+            "lattices": [f"{lat}:{order or cfg['order']}" for lat, order in lattices]}
 
 
 def summarize_prof(paths):
@@ -438,6 +443,8 @@ def main(argv=None):
     ap.add_argument("--storages", default="fp32,fp16,fp64,mom_fp32",
                     help="state storages to time; the first one is the headline value")
     ap.add_argument("--probe", action="store_true", help="short launch sequence for rocprofv3 counter runs")
+    ap.add_argument("--probe-lattices", default="D3Q27:4",
+                    help="lattice:order list of the --probe step kernels (3D lattices, 256^3 Taylor-Green fields)")
     ap.add_argument("--probe-table", action="store_true", help="HBM rates of plain access patterns, then exit")
     ap.add_argument("--summarize-prof", nargs="+", metavar="DIR", help="summarise rocprofv3 CSV output and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -466,7 +473,14 @@ def main(argv=None):
     import workloads as W
 
     if a.probe:
-        print(json.dumps(probe(P, torch, a.storages.split(","))), flush=True)
+        lats = []
+        for spec in a.probe_lattices.split(","):
+            lat, _, order = spec.partition(":")
+            if lat not in ("D3Q19", "D3Q27") or not order.isdigit():
+                print(f"bad --probe-lattices entry {spec!r} (want D3Q19:N or D3Q27:N)", file=sys.stderr)
+                return 2
+            lats.append((lat, int(order)))
+        print(json.dumps(probe(P, torch, a.storages.split(","), lattices=lats)), flush=True)
         return 0
     if a.probe_table:
         print(json.dumps(probe_table(P, torch)), flush=True)
