@@ -401,6 +401,43 @@ struct GramD3Q19Table {
   static constexpr GramD3Q19<N> t{};
 };
 
+// At order 4 the inverse Gram matrix couples the six second-order polynomials
+// S_a = H_aa (a = x, y, z) and P_ab = H_aabb through a dense 6 x 6 block that
+// is symmetric under permutations of the axes:
+//   B[S_a]  = s5 S_a  + t3 T + q2 Q + p3 P_bc    (P_bc: the pair without a)
+//   B[P_bc] = p18 P_bc + c2 T + c12 Q + s3 S_a    (S_a: the axis not in the pair)
+// with T = S_x + S_y + S_z and Q = P_xy + P_xz + P_yz, so the block takes 20
+// operations instead of 36.  The constants are read off the inverse, and
+// block_ok checks that every entry of the block has this form.
+// The block's entries are multiples of 1/3 up to the rounding of the compile-time inversion.
+constexpr double nearest_third(double x) {
+  const double n = 3.0 * x;
+  return double(static_cast<long long>(n < 0 ? n - 0.5 : n + 0.5)) / 3.0;
+}
+constexpr bool nearly(double x, double y) { return (x - y < 0 ? y - x : x - y) <= 1e-12 * (1.0 + (y < 0 ? -y : y)); }
+
+struct GramBlock19 {
+  static constexpr int S[3] = {18, 6, 2};   // (2,0,0), (0,2,0), (0,0,2)
+  static constexpr int P[3] = {8, 20, 24};  // pair without x (0,2,2), without y (2,0,2), without z (2,2,0)
+  static constexpr const double (&g)[27][27] = GramD3Q19Table<4>::t.inv;
+  static constexpr double t3 = nearest_third(g[S[2]][S[0]]), s5 = nearest_third(g[S[2]][S[2]]) - t3;
+  static constexpr double q2 = nearest_third(g[S[2]][P[0]]), p3 = nearest_third(g[S[2]][P[2]]) - q2;
+  static constexpr double c2 = nearest_third(g[P[0]][S[1]]), s3 = nearest_third(g[P[0]][S[0]]) - c2;
+  static constexpr double c12 = nearest_third(g[P[0]][P[1]]), p18 = nearest_third(g[P[0]][P[0]]) - c12;
+  static constexpr bool block_ok() {
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        if (!nearly(g[S[a]][S[b]], a == b ? s5 + t3 : t3)) return false;
+        if (!nearly(g[S[a]][P[b]], a == b ? q2 + p3 : q2)) return false;
+        if (!nearly(g[P[a]][S[b]], a == b ? c2 + s3 : c2)) return false;
+        if (!nearly(g[P[a]][P[b]], a == b ? c12 + p18 : c12)) return false;
+      }
+    return true;
+  }
+  static constexpr bool in_block(int p) { return p == 2 || p == 6 || p == 18 || p == 8 || p == 20 || p == 24; }
+};
+static_assert(GramBlock19::block_ok(), "the order-4 D3Q19 Gram block has the axis-symmetric form");
+
 // D3Q19 in FP32: the reconstruction does not keep the zeroth and first
 // moments exactly.  The constants 2/3 and 1/3 of its plain transforms are
 // rounded, which shifts the fractional bits of every rounding that follows
@@ -492,10 +529,12 @@ __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
       if constexpr (kept<L, N>(a, b, c)) B[a][b][c] = C[a][b][c];
     });
   } else {
-    // D3Q19: B = G^-1 C over the kept polynomials
+    // D3Q19: B = G^-1 C over the kept polynomials (order 4: the second-order
+    // block in its axis-symmetric form, GramBlock19)
+    constexpr bool kBlock = N >= 4;
     sfor<0, 27>([&](auto P) {
       constexpr int a = P / 9, b = (P / 3) % 3, c = P % 3;
-      if constexpr (kept<L, N>(a, b, c)) {
+      if constexpr (kept<L, N>(a, b, c) && !(kBlock && GramBlock19::in_block(P))) {
         R s = R(-0.0);
         sfor<0, 27>([&](auto S) {
           constexpr int a2 = S / 9, b2 = (S / 3) % 3, c2 = S % 3;
@@ -507,6 +546,20 @@ __device__ __forceinline__ void reconstruct(R (&C)[3][3][3], R* out) {
         B[a][b][c] = s;
       }
     });
+    if constexpr (kBlock) {
+      static_assert(N == 4, "the D3Q19 basis stops at order 4");
+      using G = GramBlock19;
+      const R sx = C[2][0][0], sy = C[0][2][0], sz = C[0][0][2];
+      const R px = C[0][2][2], py = C[2][0][2], pz = C[2][2][0];  // pair without x, y, z
+      const R T = sx + sy + sz, Q = px + py + pz;
+      const R cs = fused(R(G::t3), T, R(G::q2) * Q), cp = fused(R(G::c2), T, R(G::c12) * Q);
+      B[2][0][0] = fused(R(G::s5), sx, fused(R(G::p3), px, cs));
+      B[0][2][0] = fused(R(G::s5), sy, fused(R(G::p3), py, cs));
+      B[0][0][2] = fused(R(G::s5), sz, fused(R(G::p3), pz, cs));
+      B[0][2][2] = fused(R(G::p18), px, fused(R(G::s3), sx, cp));
+      B[2][0][2] = fused(R(G::p18), py, fused(R(G::s3), sy, cp));
+      B[2][2][0] = fused(R(G::p18), pz, fused(R(G::s3), sz, cp));
+    }
   }
   // stage z: B[a][b][*] -> G1[a][b][cz]
   constexpr int NZ = (L::D == 3) ? 3 : 1;
