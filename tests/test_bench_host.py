@@ -83,3 +83,9 @@ def test_kernel_resources_lookup(tmp_path):
     assert bench.kernel_resources(B, "fp16")["VGPRs"] == 40
     assert bench.kernel_resources(B, "fp64") is None
     assert bench.kernel_resources(types.SimpleNamespace(RESOURCES=str(tmp_path / "missing.json")), "fp32") is None
+
+
+@pytest.mark.parametrize("spec", ["D2Q9:4", "D3Q27", "D3Q19:x", "D3Q27:4,Q9:2"])
+def test_probe_lattices_are_checked_before_any_device_work(spec, capsys):
+    assert bench.main(["--probe", "--probe-lattices", spec]) == 2
+    assert "bad --probe-lattices entry" in capsys.readouterr().err
