@@ -376,7 +376,9 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
 
   auto load = [&](int z, R (&m)[NM]) {
     const S* s = src + int64_t(z) * a.sz;
-    sfor<0, NM>([&](auto C) { m[C] = at_offset(s + int64_t(C) * a.si, off_in); });
+    uint32_t o = off_in;
+    asm volatile("" : "+v"(o));  // keeps the scalar-base form of the accesses (see k_mstep_t)
+    sfor<0, NM>([&](auto C) { m[C] = at_offset(s + int64_t(C) * a.si, o); });
   };
   // Rebuild the populations of this thread's patch node into LDS; ZS selects
   // all of them (2) or only those with c_z = ZS (the planes next to a chunk).
@@ -393,7 +395,9 @@ __global__ void __launch_bounds__(MX * TY) k_mstep(const S* __restrict__ src, S*
   };
   auto put = [&](int z, const R (&m)[NM]) {
     S* d = dst + int64_t(z) * a.sz;
-    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], ptr_at_offset(d + int64_t(C) * a.si, off_out)); });
+    uint32_t o = off_out;
+    asm volatile("" : "+v"(o));
+    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], ptr_at_offset(d + int64_t(C) * a.si, o)); });
   };
   // walls (W): sides of this thread's target column and row; the side along z
   // depends on the target plane
@@ -558,7 +562,14 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_mstep_t(const S* __restrict__
 
   auto load = [&](int z, R (&m)[NM]) {
     const S* s = src + int64_t(z) * a.sz;
-    sfor<0, NM>([&](auto C) { m[C] = at_offset(s + int64_t(C) * a.si, off_in); });
+    // The empty asm hides that the lane offset is the same in every plane of
+    // the march.  Without it the compiler hoists a 64-bit copy of the offset
+    // out of the loop and adds it to every field's base with a 64-bit lane
+    // add; with it each access takes the scalar-base form (scalar field base +
+    // 32-bit lane offset) and the adds go away.
+    uint32_t o = off_in;
+    asm volatile("" : "+v"(o));
+    sfor<0, NM>([&](auto C) { m[C] = at_offset(s + int64_t(C) * a.si, o); });
   };
   auto rebuild = [&](const R (&m)[NM], auto ZS) __attribute__((always_inline)) {
     constexpr int Z = decltype(ZS)::value;
@@ -575,7 +586,9 @@ __global__ void __launch_bounds__(64 * (TY + 3)) k_mstep_t(const S* __restrict__
   };
   auto put = [&](int z, const R (&m)[NM]) {
     S* d = dst + int64_t(z) * a.sz;
-    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], ptr_at_offset(d + int64_t(C) * a.si, off_out)); });
+    uint32_t o = off_out;
+    asm volatile("" : "+v"(o));
+    sfor<0, NM>([&](auto C) { __builtin_nontemporal_store(m[C], ptr_at_offset(d + int64_t(C) * a.si, o)); });
   };
   const int wsx = W ? wall_side(a.walls, 0, x0 + lane, a.nx) : 0;
   const int wsy = W ? wall_side(a.walls, 1, y0 + r - 1, a.ny) : 0;
